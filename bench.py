@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of batched tricubic B-spline orbital VGL on one MI355X.
+
+Step = one batch of the headline workload through the whole spline path
+(lattice reduction, weights, 64-point gather-FMA, scaling, stores): an
+80^3 grid with N=384 orbitals (the NiO-32 grid and electron count of the
+paper's Table 1) in FP32, evaluated at 512 walkers x 384 electrons =
+196,608 uniform random positions.  Inputs (table and positions) are resident
+in HBM before the timed region.  Prints one JSON line.
+
+Also reported in the same line: the BF16/FP16 storage forms on the same
+workload (throughput, speedup over FP32 and error against the FP64 oracle),
+the roofline of the dominant kernel, and the FP64 CPU oracle timed on a
+bounded sample of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_UNIT = {"f32": 64 * 4 + 20, "bf16": 64 * 2 + 20, "f16": 64 * 2 + 20, "f64": 64 * 8 + 40}
+KERNEL_SOURCES = ["paper_1708_02645_amd/csrc/eval_kernel.hpp", "paper_1708_02645_amd/csrc/eval_f32.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(tile) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source and tile shape."""
+    p = os.path.join(ROOT, "profiles", "vgl_f32_80cube_n384_traffic.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash() or tuple(d.get("tile", ())) != tuple(tile):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_steps(torch, fn, steps: int, warmup: int):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")
+    ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the spline path needs no exchange between GPUs "
+              "(positions are independent and the table is read-only), and this build runs on a "
+              "single MI355X; rerun with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1708_02645_amd as q
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("bench: building C3 table (80^3, N=384) ...")
+    grid, N, coefs, _ = W.make_table(3)
+    pos_np = W.make_positions(3)
+    B = pos_np.shape[0]
+    pos = torch.from_numpy(pos_np).to(dev)
+    units = B * N
+
+    def bench_form(dtype: str, tile=None):
+        s = q.Spline(grid, coefs, dtype, device=dev)
+        out = s.alloc_outputs(B)
+        if tile:
+            s.set_tile(tile)
+        else:
+            s.autotune(pos, reps=3, out=out)
+        chosen = s.get_tile()
+        ms, wall = time_steps(torch, lambda: s.eval_vgl(pos, out=out), args.steps, args.warmup)
+        log("bench: %s tile %s  %.3f ms/step" % (dtype, chosen, ms))
+        return s, out, chosen, ms, wall
+
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    s32, out32, tile32, ms32, wall32 = bench_form("f32", tile)
+    evals = units / (ms32 * 1e-3)
+    achieved = units * BYTES_PER_UNIT["f32"] / (ms32 * 1e-3) / 1e9
+
+    # spot parity against the FP64 oracle on sampled positions (not timed)
+    import oracle
+
+    rng = np.random.default_rng(123)
+    idx = rng.choice(B, 256, replace=False)
+    it = torch.from_numpy(idx).to(dev)
+    ref = oracle.eval_vgl(grid, coefs, pos_np[idx])
+
+    def eps(out):
+        V, G, L = out
+        got = (V[it].double().cpu().numpy(), G[it].double().cpu().numpy(), L[it].double().cpu().numpy())
+        return [oracle.rel_err(g, r) for g, r in zip(got, ref)]
+
+    e32 = eps(out32)
+    del s32, out32
+    torch.cuda.empty_cache()
+
+    forms = {"f32": {"evals_per_s": evals, "ms_per_step": ms32, "tile": list(tile32),
+                     "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]}}
+    if not args.no_forms:
+        for dt in ("bf16", "f16"):
+            s, out, t, ms, _ = bench_form(dt)
+            e = eps(out)
+            forms[dt] = {"evals_per_s": units / (ms * 1e-3), "ms_per_step": ms, "tile": list(t),
+                         "speedup_vs_f32": ms32 / ms, "eps_V": e[0], "eps_G": e[1], "eps_L": e[2],
+                         "hbm_frac": units * BYTES_PER_UNIT[dt] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+            del s, out
+            torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # FP64 oracle on the host cores: a calibration run sizes a sample of
+        # about --cpu-seconds (whole batches repeated if one batch is faster).
+        ncores = len(os.sched_getaffinity(0))
+        n_cal = 256
+        t0 = time.perf_counter()
+        oracle.eval_vgl(grid, coefs, pos_np[:n_cal], threads=ncores)
+        per_pos = (time.perf_counter() - t0) / n_cal
+        want = int(args.cpu_seconds / max(per_pos, 1e-9))
+        n = min(B, max(n_cal, want))
+        reps = max(1, min(20, want // B)) if want > B else 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.eval_vgl(grid, coefs, pos_np[:n], threads=ncores)
+        dt = time.perf_counter() - t0
+        cpu = {"value": reps * n * N / dt, "unit": "orbital-VGL/s", "cores": ncores, "kind": "oracle",
+               "sample": "%d x the first %d of the %d positions of the same workload, all %d orbitals; "
+                         "FP64 oracle (plain loops, OpenMP over positions, gcc -O2), %.1f s wall"
+                         % (reps, n, B, N, dt)}
+
+    traffic = traffic_from_profiles(tile32)
+    line = {
+        "metric": "orbital-VGL evals/s and % HBM peak; MLP/BF16 vs FP32 spline speedup at fixed err",
+        "value": evals,
+        "unit": "orbital-VGL/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: plane-wave orbitals fitted on the grid, uniform random positions (seeded)",
+        "config": {"workload": "80^3 periodic grid, N=384 orbitals, FP32 table; 512 walkers x 384 "
+                               "electrons = 196608 positions per batch, one VGL each",
+                   "grid": list(grid), "norb": N, "positions": B, "table": "f32", "tile": list(tile32),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "bytes_per_unit": BYTES_PER_UNIT["f32"], "units_per_launch": units},
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "wall_s_timed": wall32,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,75 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// the qmcspline library.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/qmcspline.h"
+
+namespace qs {
+
+// Thread-local last-error text and helpers that set it.
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define QS_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return qs::hip_fail(e_, #call); \
+    } while (0)
+
+// Kernel arguments of the single-table evaluation kernels.  The same
+// struct serves VGL and value-only launches.
+struct EvalArgs {
+    const unsigned char* table;  // row (0,0,0) of the halo layout
+    const float* scales;         // per-orbital scale (16-bit stores), else unused
+    const double* pos;           // [B][3]
+    void* V;                     // [B][norb]
+    void* G;                     // [B][3][norb]
+    void* L;                     // [B][norb]
+    int64_t B;
+    int64_t row_bytes;  // bytes per grid point row
+    int64_t ystride;    // bytes between consecutive y rows (padded z extent * row_bytes)
+    int64_t xstride;    // bytes between consecutive x planes
+    double cell[3];
+    int32_t n[3];
+    int32_t norb;
+    int32_t tiles;      // orbital tiles per position
+    int32_t pb;         // positions per workgroup
+};
+
+// One compiled kernel variant.
+using KernelFn = void (*)(EvalArgs);
+struct Variant {
+    spline_dtype store;
+    int cw, nch, lpp;
+    bool vgl;         // true: V, G, L; false: value only
+    const void* fn;   // __global__ function symbol
+    size_t lds_per_pos;
+};
+
+// Registry of every compiled variant (filled by the kernel files).
+const Variant* variants(int* count);
+
+// Launch one variant; validates nothing (the caller did).
+int launch(const Variant& v, const EvalArgs& a, hipStream_t stream);
+
+constexpr int kBlock = 256;  // threads per workgroup of the evaluation kernels
+
+}  // namespace qs
+
+// Handle (opaque in the C ABI).
+struct spline_s {
+    spline_grid grid;
+    int32_t norb;
+    spline_dtype store;
+    spline_layout layout;
+    unsigned char* dev;    // caller's device buffer
+    int device;            // HIP device id the table lives on
+    spline_tile tile;      // current VGL tile shape
+    spline_tile vtile;     // current value-only tile shape
+};

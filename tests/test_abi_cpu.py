@@ -1,0 +1,142 @@
+"""CPU-side checks of the C ABI: exported symbols, layout arithmetic,
+argument validation, and the host packing (halo layout + quantization),
+which is integer/byte work and must match the oracle's dequantized table
+bit for bit.  No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1708_02645_amd as q
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "qmcspline.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spline_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_symbol():
+    names = header_functions()
+    assert len(names) >= 12
+    L = q.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_layout_and_sizes():
+    L = q.get_layout((80, 80, 80), 384, "f32")
+    assert L.row_bytes == 1536 and L.n_pad == 384
+    assert L.table_bytes == 83 ** 3 * 1536
+    assert L.total_bytes == L.table_bytes + 1536  # 384 float scales, already 256-aligned
+    assert tuple(L.padded) == (83, 83, 83)
+    L = q.get_layout((16, 16, 16), 32, "f64")
+    assert L.row_bytes == 256 and L.n_pad == 32
+    L = q.get_layout((5, 6, 7), 37, "bf16")
+    assert L.row_bytes == 256 and L.n_pad == 128
+    assert q.table_bytes((5, 6, 7), 37, "bf16") == L.total_bytes
+
+
+@pytest.mark.parametrize("args", [
+    ((0, 4, 4), 4, "f32", (1, 1, 1)),
+    ((4, 4, 4), 0, "f32", (1, 1, 1)),
+    ((4, 4, 4), 4, "f32", (1, 0, 1)),
+    ((4, 4, 4), 4, "f32", (1, float("inf"), 1)),
+    ((4, 4, 4), 4, "f32", (1, float("nan"), 1)),
+    ((1 << 20, 1 << 20, 1 << 20), 1 << 30, "f64", (1, 1, 1)),  # overflow
+])
+def test_invalid_sizes_return_zero_bytes(args):
+    grid, n, dt, cell = args
+    assert q.table_bytes(grid, n, dt, cell) == 0
+    with pytest.raises(q.SplineError) as e:
+        q.get_layout(grid, n, dt, cell)
+    assert e.value.code in (-1, -2)
+    assert q.last_error()
+
+
+def test_null_and_bad_arguments():
+    L = q.lib()
+    g = q.make_grid((4, 4, 4))
+    h = ctypes.c_void_p()
+    c = np.zeros((4, 4, 4, 2))
+    assert L.spline_create(None, 2, c.ctypes.data, 1, None, 0, None, ctypes.byref(h)) == -1
+    assert L.spline_create(ctypes.byref(g), 2, None, 1, None, 0, None, ctypes.byref(h)) == -1
+    assert "NULL" in q.last_error() or "null" in q.last_error().lower()
+    assert L.spline_create(ctypes.byref(g), 2, c.ctypes.data, 7, None, 0, None, ctypes.byref(h)) == -1
+    assert L.spline_create(ctypes.byref(g), 2, c.ctypes.data, 1, ctypes.c_void_p(256), 16, None,
+                           ctypes.byref(h)) == -2  # buffer too small
+    assert L.spline_create(ctypes.byref(g), 2, c.ctypes.data, 1, ctypes.c_void_p(260), 1 << 20, None,
+                           ctypes.byref(h)) == -1  # misaligned
+    assert L.spline_create(ctypes.byref(g), 2, c.ctypes.data, 1, None, 0, None, None) == -1
+    assert L.spline_eval_vgl(None, None, 0, None, None, None, None) == -1
+    assert L.spline_destroy(None) == 0
+    assert L.spline_get_tile(None, None) == -1
+    assert L.spline_autotune(None, None, 0, None, None, None, 1, None, None, None) == -1
+
+
+def test_pack_rejects_nonfinite():
+    c = np.zeros((3, 3, 3, 2))
+    c[1, 1, 1, 1] = np.nan
+    for dt in ("f64", "f32", "bf16", "f16"):
+        with pytest.raises(q.SplineError):
+            q.pack_host((3, 3, 3), c, dt)
+
+
+def _unpack(buf, grid, norb, dtype):
+    """Decode the halo table and scales of a packed buffer (numpy only)."""
+    L = q.get_layout(grid, norb, dtype)
+    P = tuple(L.padded)
+    rows = np.frombuffer(buf[:L.table_bytes].tobytes(), dtype=np.uint8).reshape(P + (L.row_bytes,))
+    sc = np.frombuffer(buf[L.scales_offset:L.scales_offset + 4 * L.n_pad].tobytes(), dtype=np.float32)
+    if dtype == "f64":
+        vals = rows.view(np.float64)
+    elif dtype == "f32":
+        vals = rows.view(np.float32).astype(np.float64)
+    elif dtype == "f16":
+        vals = rows.view(np.float16).astype(np.float64)
+    else:
+        u = rows.view(np.uint16).astype(np.uint32) << 16
+        vals = u.view(np.float32).astype(np.float64)
+    return vals, sc.astype(np.float64), L
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_pack_matches_oracle_dequantized_bitwise(oracle, dtype):
+    rng = np.random.default_rng(21)
+    grid, norb = (5, 3, 6), 37
+    c = rng.standard_normal(grid + (norb,)) * np.exp(rng.uniform(-12, 6, norb))
+    c[..., 5] = 0.0                  # all-zero orbital -> scale 1
+    c[..., 6] *= 1e-3                # includes FP16 subnormals after scaling
+    c[0, 0, 0, 6] = 1.0
+    buf = q.pack_host(grid, c, dtype)
+    vals, sc, L = _unpack(buf, grid, norb, dtype)
+    dq, s_or = oracle.dequantize(c, dtype)
+    np.testing.assert_array_equal(sc[:norb], s_or)
+    assert (sc[norb:] == 1.0).all()
+    n = np.array(grid)
+    for p0 in range(grid[0] + 3):
+        for p1 in range(grid[1] + 3):
+            for p2 in range(grid[2] + 3):
+                j = ((p0 - 1) % n[0], (p1 - 1) % n[1], (p2 - 1) % n[2])
+                got = vals[p0, p1, p2, :norb] * sc[:norb]
+                np.testing.assert_array_equal(got, dq[j])
+                assert (vals[p0, p1, p2, norb:] == 0).all()
+
+
+def test_pack_f16_ties_and_extremes(oracle):
+    """Values at exact rounding ties and at the FP16 subnormal edge."""
+    c = np.zeros((1, 1, 1, 4))
+    c[0, 0, 0, 0] = 1.0                         # scale 1
+    c[0, 0, 0, 1] = 1.0 + 2.0 ** -11            # tie -> even (1.0), scale 2 -> 0.5+2^-12: tie too
+    c[0, 0, 0, 2] = -(2.0 ** -25) * 3           # below half of the smallest subnormal after scale
+    c[0, 0, 0, 3] = 2.0 ** -14 + 2.0 ** -25     # near the normal/subnormal boundary
+    for dt in ("f16", "bf16"):
+        buf = q.pack_host((1, 1, 1), c, dt)
+        vals, sc, L = _unpack(buf, (1, 1, 1), 4, dt)
+        dq, _ = oracle.dequantize(c, dt)
+        np.testing.assert_array_equal(vals[1, 1, 1, :4] * sc[:4], dq[0, 0, 0])
