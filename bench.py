@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_UNIT = {"f32": 64 * 4 + 20, "bf16": 64 * 2 + 20, "f16": 64 * 2 + 20, "f64": 64 * 8 + 40}
+TUNE_CACHE = os.path.join(ROOT, "paper_1708_02645_amd", "tune_cache.txt")
 KERNEL_SOURCES = ["paper_1708_02645_amd/csrc/eval_kernel.hpp", "paper_1708_02645_amd/csrc/eval_f32.hip"]
 
 
@@ -81,7 +82,30 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
+    ap.add_argument("--no-tune-cache", dest="use_tune_cache", action="store_false",
+                    help="search tile shapes afresh instead of reading the committed tuning cache")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_probe_bytes": n, "launches": 6, "ms": ms, "GBs_read_plus_write": 2 * n / ms / 1e6}),
+              flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -111,7 +135,8 @@ def main() -> int:
         if tile:
             s.set_tile(tile)
         else:
-            s.autotune(pos, reps=3, out=out)
+            # the autotuner; its committed cache makes the choice repeatable
+            s.autotune(pos, reps=3, out=out, cache_path=TUNE_CACHE if args.use_tune_cache else None)
         chosen = s.get_tile()
         ms, wall = time_steps(torch, lambda: s.eval_vgl(pos, out=out), args.steps, args.warmup)
         log("bench: %s tile %s  %.3f ms/step" % (dtype, chosen, ms))
