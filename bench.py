@@ -79,6 +79,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 forms")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the four-table ragged plan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
@@ -175,6 +176,37 @@ def main() -> int:
                          "hbm_frac": units * BYTES_PER_UNIT[dt] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
             del s, out
             torch.cuda.empty_cache()
+
+    if not args.no_ragged:
+        # Ragged workload: four tables (32^3/48^3/64^3/80^3, N = 64/128/256/384,
+        # FP32) with U{64..1024} walkers each, in one graph-captured
+        # persistent launch, against the same work as four tuned launches.
+        log("bench: building the four ragged tables ...")
+        tabs = W.make_ragged()
+        sp = [q.Spline(t["grid"], t["coefs"], "f32", device=dev) for t in tabs]
+        ps = [torch.from_numpy(t["pos"]).to(dev) for t in tabs]
+        del tabs
+        plan = q.Plan(sp, ps, tune_reps=3)
+        units_r = sum(p.shape[0] * s.norb for s, p in zip(sp, ps))
+        ms_plan, _ = time_steps(torch, plan.launch, args.steps, args.warmup)
+        for s, p, o in zip(sp, ps, plan.outs):
+            s.autotune(p, reps=2, out=o)
+
+        def separate():
+            for s, p, o in zip(sp, ps, plan.outs):
+                s.eval_vgl(p, out=o)
+
+        ms_sep, _ = time_steps(torch, separate, args.steps, args.warmup)
+        info = plan.info()
+        forms["ragged_4_tables_f32"] = {
+            "positions": [int(p.shape[0]) for p in ps], "norb": [s.norb for s in sp],
+            "evals_per_s": units_r / (ms_plan * 1e-3), "ms_per_launch": ms_plan,
+            "ms_four_separate_launches": ms_sep, "speedup_vs_separate": ms_sep / ms_plan,
+            "hbm_frac": units_r * BYTES_PER_UNIT["f32"] / (ms_plan * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "tile": list(info["tile"]), "tasks": info["tasks"], "persistent_workgroups": info["blocks"]}
+        log("bench: ragged plan %.3f ms vs separate %.3f ms" % (ms_plan, ms_sep))
+        del plan, sp, ps
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -147,6 +147,53 @@ int spline_get_tile(const spline_t* s, spline_tile* tile);
 int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
                     int32_t reps, const char* cache_path, void* stream, spline_tile* chosen);
 
+/* ---- Ragged multi-table plans --------------------------------------------
+ * The walker population fluctuates from generation to generation and each
+ * walker carries its own electrons (Section 6 and Algorithm 1: per-walker
+ * loops over a variable N_w), and a workload may hold several tables; the
+ * paper proposes tiling the large table and evaluating the tiles in parallel
+ * (Section 8.4).  A plan evaluates B[t] positions of each of n_tabs tables
+ * (same storage type, same device) in ONE persistent work-queue launch:
+ * workgroups pop (table, position block) tasks from a device counter, widest
+ * tables first.  The launch (a counter-reset kernel and the persistent
+ * kernel) is captured once into a HIP graph at creation; every
+ * spline_plan_launch is one graph launch.  The plan is bound to the given
+ * position and output buffers (same shapes and element types as
+ * spline_eval_vgl) and to the workspace; their contents may change between
+ * launches, their addresses may not.  Concurrent launches of one plan race on
+ * its workspace. */
+typedef struct spline_plan_s spline_plan_t;
+
+/* Device workspace bytes a plan over these batch sizes needs (counter, table
+ * descriptors, task list); 0 on invalid input. */
+size_t spline_plan_workspace_bytes(int32_t n_tabs, const int64_t* B_per_tab);
+
+/* Creates a plan.  tabs[n_tabs]: handles (not owned); B_per_tab[t] >= 0;
+ * pos_dev[t], V[t], G[t], L[t]: device buffers of table t (may be NULL when
+ * B_per_tab[t] == 0); workspace_dev: caller-owned device buffer of at least
+ * spline_plan_workspace_bytes() bytes, 256-byte aligned, alive as long as
+ * the plan.  tune_reps > 0 times every shape that divides all tables' rows
+ * (tune_reps launches each) and keeps the fastest, after checking that all
+ * give bit-identical outputs; 0 takes a default.  The tuning launches write
+ * the outputs.  Synchronises `stream`. */
+int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+                       const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
+                       void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
+                       spline_plan_t** out);
+
+/* One replay of the captured graph on `stream` (asynchronous). */
+int spline_plan_launch(const spline_plan_t* plan, void* stream);
+
+/* The same two kernels launched directly, without the graph (for checking
+ * the graph against eager execution). */
+int spline_plan_launch_eager(const spline_plan_t* plan, void* stream);
+
+/* Chosen tile shape, number of tasks and of persistent workgroups. */
+int spline_plan_get_info(const spline_plan_t* plan, spline_tile* tile, int32_t* n_tasks, int32_t* n_blocks);
+
+/* Releases the graph and the handle (not the workspace). NULL is accepted. */
+int spline_plan_destroy(spline_plan_t* plan);
+
 /* Handle metadata queries. */
 int spline_get_info(const spline_t* s, spline_grid* grid, int32_t* n_orb, spline_dtype* store,
                     spline_layout* layout);

@@ -69,6 +69,12 @@ def lib():
             "spline_get_info": ([p, p, p, p, p], ctypes.c_int),
             "spline_destroy": ([p], ctypes.c_int),
             "spline_last_error": ([], ctypes.c_char_p),
+            "spline_plan_workspace_bytes": ([i32, p], sz),
+            "spline_plan_create": ([p, i32, p, p, p, p, p, p, sz, i32, p, p], ctypes.c_int),
+            "spline_plan_launch": ([p, p], ctypes.c_int),
+            "spline_plan_launch_eager": ([p, p], ctypes.c_int),
+            "spline_plan_get_info": ([p, p, p, p], ctypes.c_int),
+            "spline_plan_destroy": ([p], ctypes.c_int),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -239,6 +245,73 @@ class Spline:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().spline_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Ragged multi-table evaluation: one persistent launch captured in a HIP
+    graph.  splines: list of Spline (same storage type); positions: list of
+    float64 [B_t, 3] device tensors (B_t may be 0).  Outputs are allocated
+    here (or passed as a list of (V, G, L)) and stay bound to the plan."""
+
+    def __init__(self, splines, positions, outs=None, tune_reps: int = 3, stream=None):
+        import torch
+
+        self._torch = torch
+        n = len(splines)
+        if n == 0 or len(positions) != n:
+            raise ValueError("need one positions tensor per table")
+        self.splines = list(splines)
+        self.positions = [s._pos(p) for s, p in zip(splines, positions)]
+        self.outs = list(outs) if outs is not None else [s.alloc_outputs(p.shape[0]) for s, p in zip(splines, positions)]
+        dev = splines[0].device
+        Bs = (ctypes.c_int64 * n)(*[p.shape[0] for p in self.positions])
+        nb = int(lib().spline_plan_workspace_bytes(n, Bs))
+        if nb == 0:
+            check(-1)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        vp = ctypes.c_void_p
+        tabs = (vp * n)(*[s.handle.value for s in splines])
+        pos = (vp * n)(*[p.data_ptr() for p in self.positions])
+        V = (vp * n)(*[o[0].data_ptr() for o in self.outs])
+        G = (vp * n)(*[o[1].data_ptr() for o in self.outs])
+        L = (vp * n)(*[o[2].data_ptr() for o in self.outs])
+        h = vp()
+        L_ = lib()
+        with torch.cuda.device(dev):
+            sp, _ = _stream_ptr(torch, dev, stream)
+            check(L_.spline_plan_create(tabs, n, Bs, pos, V, G, L, vp(self.ws.data_ptr()), nb, int(tune_reps), sp,
+                                        ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+
+    def launch(self, stream=None):
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_plan_launch(self._h, sp))
+        return self.outs
+
+    def launch_eager(self, stream=None):
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_plan_launch_eager(self._h, sp))
+        return self.outs
+
+    def info(self):
+        t = Tile()
+        nt, nb = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spline_plan_get_info(self._h, ctypes.byref(t), ctypes.byref(nt), ctypes.byref(nb)))
+        return {"tile": t.astuple(), "tasks": nt.value, "blocks": nb.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().spline_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -42,13 +42,29 @@ struct EvalArgs {
     int32_t pb;         // positions per workgroup
 };
 
+// One task of a multi-table plan: positions [first, first + count) of table
+// `table` (count <= the plan's positions per workgroup).
+struct PlanTask {
+    int32_t table;
+    int32_t count;
+    int64_t first;
+};
+
+// Kernel arguments of the persistent multi-table kernel.
+struct PlanArgs {
+    const EvalArgs* tabs;   // device, one per table
+    const PlanTask* tasks;  // device, ntasks entries, processed in order of popping
+    unsigned int* counter;  // device work counter, zero at launch
+    int32_t ntasks;
+};
+
 // One compiled kernel variant.
-using KernelFn = void (*)(EvalArgs);
 struct Variant {
     spline_dtype store;
     int cw, nch, lpp;
-    bool vgl;         // true: V, G, L; false: value only
-    const void* fn;   // __global__ function symbol
+    bool vgl;              // true: V, G, L; false: value only
+    const void* fn;        // __global__ function symbol (single table)
+    const void* plan_fn;   // persistent multi-table kernel (VGL variants only), else null
     size_t lds_per_pos;
 };
 
@@ -59,6 +75,20 @@ const Variant* variants(int* count);
 int launch(const Variant& v, const EvalArgs& a, hipStream_t stream);
 
 constexpr int kBlock = 256;  // threads per workgroup of the evaluation kernels
+
+}  // namespace qs
+
+struct spline_s;
+
+namespace qs {
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out);
+// Whole tiles of variant v cover the padded rows of table s exactly.
+bool tile_fits(const spline_s* s, const Variant& v);
+const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl);
+int64_t tiles_of(const spline_s* s, const spline_tile& t);
+EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G,
+                   void* L);
 
 }  // namespace qs
 

@@ -6,9 +6,9 @@ namespace qs {
 
 #define QS_VARIANT(CW, NCH, LPP)                                                          \
     {SPL_F16, CW, NCH, LPP, true, (const void*)&eval_kernel<SPL_F16, CW, NCH, LPP, true>,          \
-     sizeof(PosW<Acc<SPL_F16>::type>)},                                                      \
+     (const void*)&plan_kernel<SPL_F16, CW, NCH, LPP>, sizeof(PosW<Acc<SPL_F16>::type>)},            \
     {SPL_F16, CW, NCH, LPP, false, (const void*)&eval_kernel<SPL_F16, CW, NCH, LPP, false>,        \
-     sizeof(PosW<Acc<SPL_F16>::type>)},
+     nullptr, sizeof(PosW<Acc<SPL_F16>::type>)},
 
 static const Variant k_variants[] = {
     QS_VARIANT(1, 1, 64)

@@ -6,9 +6,9 @@ namespace qs {
 
 #define QS_VARIANT(CW, NCH, LPP)                                                          \
     {SPL_F64, CW, NCH, LPP, true, (const void*)&eval_kernel<SPL_F64, CW, NCH, LPP, true>,          \
-     sizeof(PosW<Acc<SPL_F64>::type>)},                                                      \
+     (const void*)&plan_kernel<SPL_F64, CW, NCH, LPP>, sizeof(PosW<Acc<SPL_F64>::type>)},            \
     {SPL_F64, CW, NCH, LPP, false, (const void*)&eval_kernel<SPL_F64, CW, NCH, LPP, false>,        \
-     sizeof(PosW<Acc<SPL_F64>::type>)},
+     nullptr, sizeof(PosW<Acc<SPL_F64>::type>)},
 
 static const Variant k_variants[] = {
     QS_VARIANT(2, 1, 64)

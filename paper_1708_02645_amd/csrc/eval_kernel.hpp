@@ -197,8 +197,11 @@ __device__ inline void store_vals(TA* dst, const TA* v, int o, int norb, bool al
     }
 }
 
+// Evaluates positions [b0, b0 + np) of one table with the whole workgroup.
+// W: LDS staging for at least np positions.  Contains one workgroup barrier
+// (between staging and evaluation); callers that reuse W must barrier again.
 template <spline_dtype S, int CW, int NCH, int LPP, bool VGL>
-__global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
+__device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<typename Acc<S>::type>* W)
 {
     using TA = typename Acc<S>::type;
     constexpr int VPC = vals_per_chunk<S>(CW);  // values per chunk per lane
@@ -209,14 +212,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
     constexpr int TO = LPP * VPL;               // tile orbitals
     static_assert(VPC >= 1, "chunk narrower than one value");
 
-    extern __shared__ unsigned char lds_raw[];
-    PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
-
     const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * a.pb;
-    const int64_t rem = a.B - b0;
-    const int np = rem < a.pb ? (int)rem : a.pb;
-
     for (int p = tid; p < np; p += kBlock) stage_position<TA>(a, b0 + p, W[p]);
     __syncthreads();
 
@@ -406,6 +402,43 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
 #pragma unroll
             for (int q = 0; q < (VGL ? 5 : 1); ++q) store_vals<TA, VPC>(r[q], &acc[q][c * VPC], o, a.norb, aligned);
         }
+    }
+}
+
+// One table: workgroup i takes positions [i*pb, i*pb + pb).
+template <spline_dtype S, int CW, int NCH, int LPP, bool VGL>
+__global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
+{
+    using TA = typename Acc<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
+    const int64_t b0 = (int64_t)blockIdx.x * a.pb;
+    const int64_t rem = a.B - b0;
+    const int np = rem < a.pb ? (int)rem : a.pb;
+    eval_block<S, CW, NCH, LPP, VGL>(a, b0, np, W);
+}
+
+// Several tables in one launch (ragged batches): a persistent grid pops
+// tasks (table, first position, count <= pb) from a device counter until the
+// list is exhausted.  Every workgroup exits once the counter passes ntasks,
+// so the grid always drains.  The counter must be zero at launch
+// (plan_reset_kernel, captured in the same graph).
+template <spline_dtype S, int CW, int NCH, int LPP>
+__global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs pa)
+{
+    using TA = typename Acc<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
+    __shared__ int s_task;
+    for (;;) {
+        if (threadIdx.x == 0) s_task = (int)atomicAdd(pa.counter, 1u);
+        __syncthreads();
+        const int t = uniform<int>(s_task);
+        if (t >= pa.ntasks) break;  // uniform across the workgroup
+        const PlanTask tk = pa.tasks[t];
+        const EvalArgs a = pa.tabs[tk.table];
+        eval_block<S, CW, NCH, LPP, true>(a, tk.first, tk.count, W);
+        __syncthreads();  // W and s_task are rewritten by the next task
     }
 }
 

@@ -1,0 +1,352 @@
+// Ragged multi-table plans: several tables with their own batch sizes
+// evaluated by one persistent work-queue launch, captured once in a HIP
+// graph and replayed with a single graph launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace qs {
+
+// Zeroes the work counter of a plan (a kernel, not a memset node, so that the
+// captured graph holds only kernel nodes).
+__global__ void plan_reset_kernel(unsigned int* counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+constexpr int kMinPb = 16;  // smallest positions-per-task; sizes the workspace
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct WsLayout {
+    size_t counter, tabs, tasks, total;
+};
+
+static bool ws_layout(int32_t n_tabs, const int64_t* B, WsLayout* w, int64_t* max_tasks)
+{
+    int64_t nt = 0;
+    for (int32_t t = 0; t < n_tabs; ++t) {
+        if (B[t] < 0) return false;
+        nt += (B[t] + kMinPb - 1) / kMinPb;
+        if (nt > (int64_t)1 << 30) return false;
+    }
+    w->counter = 0;
+    w->tabs = 256;
+    w->tasks = w->tabs + align256((size_t)n_tabs * sizeof(EvalArgs));
+    w->total = w->tasks + align256((size_t)std::max<int64_t>(nt, 1) * sizeof(PlanTask));
+    *max_tasks = nt;
+    return true;
+}
+
+}  // namespace qs
+
+struct spline_plan_s {
+    std::vector<const spline_s*> tabs;
+    std::vector<int64_t> B;
+    std::vector<const double*> pos;
+    std::vector<void*> V, G, L;
+    unsigned char* ws = nullptr;
+    qs::WsLayout lay{};
+    spline_tile tile{};
+    const qs::Variant* var = nullptr;
+    int32_t ntasks = 0;
+    int32_t nblocks = 0;
+    int device = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace qs {
+
+// Builds the task list for positions-per-task pb: tables with the widest
+// rows first (largest tasks first, the narrow ones fill the tail).
+static std::vector<PlanTask> make_tasks(const spline_plan_s* p, int pb)
+{
+    std::vector<int32_t> order(p->tabs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return p->tabs[a]->layout.row_bytes > p->tabs[b]->layout.row_bytes;
+    });
+    std::vector<PlanTask> tasks;
+    for (int32_t t : order)
+        for (int64_t f = 0; f < p->B[t]; f += pb)
+            tasks.push_back(PlanTask{t, (int32_t)std::min<int64_t>(pb, p->B[t] - f), f});
+    return tasks;
+}
+
+// Uploads the descriptors and tasks for (variant, tile) and sizes the grid.
+static int stage_config(spline_plan_s* p, const Variant* v, const spline_tile& t, hipStream_t st)
+{
+    std::vector<EvalArgs> args(p->tabs.size());
+    for (size_t i = 0; i < p->tabs.size(); ++i) {
+        args[i] = make_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
+    }
+    std::vector<PlanTask> tasks = make_tasks(p, t.pb);
+    QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(EvalArgs),
+                          hipMemcpyHostToDevice, st));
+    if (!tasks.empty())
+        QS_HIP(hipMemcpyAsync(p->ws + p->lay.tasks, tasks.data(), tasks.size() * sizeof(PlanTask),
+                              hipMemcpyHostToDevice, st));
+    QS_HIP(hipStreamSynchronize(st));  // the host vectors die at return
+    const size_t lds = v->lds_per_pos * (size_t)t.pb;
+    int per_cu = 0;
+    QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->plan_fn, kBlock, lds));
+    hipDeviceProp_t prop;
+    QS_HIP(hipGetDeviceProperties(&prop, p->device));
+    const int64_t full = (int64_t)std::max(per_cu, 1) * prop.multiProcessorCount;
+    p->ntasks = (int32_t)tasks.size();
+    p->nblocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(full, p->ntasks));
+    p->var = v;
+    p->tile = t;
+    return SPL_OK;
+}
+
+static int launch_plan(const spline_plan_s* p, hipStream_t st)
+{
+    if (p->ntasks == 0) return SPL_OK;
+    unsigned int* counter = reinterpret_cast<unsigned int*>(p->ws + p->lay.counter);
+    hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+    QS_HIP(hipGetLastError());
+    PlanArgs pa{reinterpret_cast<const EvalArgs*>(p->ws + p->lay.tabs),
+                reinterpret_cast<const PlanTask*>(p->ws + p->lay.tasks), counter, p->ntasks};
+    void* params[] = {&pa};
+    const size_t lds = p->var->lds_per_pos * (size_t)p->tile.pb;
+    QS_HIP(hipLaunchKernel(p->var->plan_fn, dim3(p->nblocks), dim3(kBlock), params, lds, st));
+    QS_HIP(hipGetLastError());
+    return SPL_OK;
+}
+
+// Copies the first rows of every table's outputs to the host (autotuner check).
+static int sample_outputs(const spline_plan_s* p, std::vector<unsigned char>& out, hipStream_t st)
+{
+    out.clear();
+    for (size_t i = 0; i < p->tabs.size(); ++i) {
+        const int64_t rows = std::min<int64_t>(p->B[i], 64);
+        if (rows == 0) continue;
+        const size_t es = p->tabs[i]->store == SPL_F64 ? 8 : 4;
+        const size_t n = (size_t)rows * p->tabs[i]->norb * es;
+        const size_t at = out.size();
+        out.resize(at + 5 * n);
+        QS_HIP(hipMemcpyAsync(out.data() + at, p->V[i], n, hipMemcpyDeviceToHost, st));
+        QS_HIP(hipMemcpyAsync(out.data() + at + n, p->G[i], 3 * n, hipMemcpyDeviceToHost, st));
+        QS_HIP(hipMemcpyAsync(out.data() + at + 4 * n, p->L[i], n, hipMemcpyDeviceToHost, st));
+    }
+    QS_HIP(hipStreamSynchronize(st));
+    return SPL_OK;
+}
+
+static void free_graph(spline_plan_s* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+extern "C" {
+
+size_t spline_plan_workspace_bytes(int32_t n_tabs, const int64_t* B_per_tab)
+{
+    if (n_tabs <= 0 || !B_per_tab) return 0;
+    WsLayout w;
+    int64_t nt = 0;
+    if (!ws_layout(n_tabs, B_per_tab, &w, &nt)) return 0;
+    return w.total;
+}
+
+int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+                       const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
+                       void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
+                       spline_plan_t** out)
+{
+    if (!out) return fail(SPL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_tabs <= 0 || n_tabs > 4096) return fail(SPL_EINVAL, "n_tabs must be in [1, 4096]");
+    if (!tabs || !B_per_tab || !pos_dev || !V || !G || !L) return fail(SPL_EINVAL, "NULL array argument");
+    if (!workspace_dev) return fail(SPL_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace_dev) & 255) != 0)
+        return fail(SPL_EINVAL, "workspace not 256-byte aligned");
+    WsLayout lay;
+    int64_t max_tasks = 0;
+    if (!ws_layout(n_tabs, B_per_tab, &lay, &max_tasks)) return fail(SPL_EINVAL, "negative or huge batch size");
+    if (workspace_bytes < lay.total) return fail(SPL_ENOMEM, "workspace smaller than spline_plan_workspace_bytes()");
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    for (int32_t t = 0; t < n_tabs; ++t) {
+        if (!tabs[t]) return fail(SPL_EINVAL, "NULL table handle");
+        if (tabs[t]->store != tabs[0]->store) return fail(SPL_EUNSUPPORTED, "tables of one plan must share the storage type");
+        if (tabs[t]->device != dev) return fail(SPL_EINVAL, "table lives on another device");
+        if (B_per_tab[t] > 0 && (!pos_dev[t] || !V[t] || !G[t] || !L[t]))
+            return fail(SPL_EINVAL, "NULL position or output pointer");
+        int64_t tmp;
+        if (!mul_ok(B_per_tab[t], (int64_t)tabs[t]->norb * 3 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    }
+    spline_plan_s* p = new (std::nothrow) spline_plan_s;
+    if (!p) return fail(SPL_ENOMEM, "plan allocation failed");
+    p->tabs.assign(tabs, tabs + n_tabs);
+    p->B.assign(B_per_tab, B_per_tab + n_tabs);
+    p->pos.assign(pos_dev, pos_dev + n_tabs);
+    p->V.assign(V, V + n_tabs);
+    p->G.assign(G, G + n_tabs);
+    p->L.assign(L, L + n_tabs);
+    p->ws = static_cast<unsigned char*>(workspace_dev);
+    p->lay = lay;
+    p->device = dev;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    // Candidate shapes: tiles that divide every table's row, times pb.
+    std::vector<std::pair<const Variant*, spline_tile>> cands;
+    int nv = 0;
+    const Variant* vs = variants(&nv);
+    for (int i = 0; i < nv; ++i) {
+        const Variant& v = vs[i];
+        if (!v.vgl || !v.plan_fn || v.store != tabs[0]->store) continue;
+        bool ok = true;
+        for (int32_t t = 0; t < n_tabs && ok; ++t) ok = tile_fits(tabs[t], v);
+        if (!ok) continue;
+        for (int pb : {16, 32, 64}) {
+            if (v.lds_per_pos * (size_t)pb > 64 * 1024) continue;
+            cands.push_back({&v, spline_tile{v.cw, v.nch, v.lpp, pb}});
+        }
+    }
+    if (cands.empty()) {
+        delete p;
+        return fail(SPL_EUNSUPPORTED, "no compiled tile shape divides every table's row");
+    }
+    // Without tuning: the first table's own default shape if it fits all, else
+    // the widest-chunk candidate with positions-per-task 32.
+    size_t pick = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const spline_tile& d = tabs[0]->tile;
+        if (cands[i].second.cw == d.cw && cands[i].second.nch == d.nch && cands[i].second.lpp == d.lpp &&
+            cands[i].second.pb == 32) {
+            pick = i;
+            break;
+        }
+        if (cands[i].second.pb == 32 && cands[i].second.cw * cands[i].second.nch >
+                                            cands[pick].second.cw * cands[pick].second.nch)
+            pick = i;
+    }
+    int rc = SPL_OK;
+    if (tune_reps > 0 && max_tasks > 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            delete p;
+            return fail(SPL_EHIP, "hipEventCreate failed");
+        }
+        std::vector<unsigned char> ref, cur;
+        float best = 1e30f;
+        for (size_t i = 0; i < cands.size() && rc == SPL_OK; ++i) {
+            rc = stage_config(p, cands[i].first, cands[i].second, st);
+            if (!rc) rc = launch_plan(p, st);
+            if (!rc) rc = sample_outputs(p, i == 0 ? ref : cur, st);
+            if (rc) break;
+            if (i > 0 && cur != ref) {
+                std::ostringstream m;
+                m << "plan autotune: tile (" << cands[i].second.cw << "," << cands[i].second.nch << ","
+                  << cands[i].second.lpp << "," << cands[i].second.pb << ") differs bitwise from the first";
+                rc = fail(SPL_EUNSUPPORTED, m.str());
+                break;
+            }
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SPL_EHIP, "event record"); break; }
+            for (int r = 0; r < tune_reps && !rc; ++r) rc = launch_plan(p, st);
+            float ms = 0.f;
+            if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(SPL_EHIP, "plan autotune: event timing failed");
+            if (!rc && ms < best) {
+                best = ms;
+                pick = i;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    if (!rc) rc = stage_config(p, cands[pick].first, cands[pick].second, st);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+
+    // Capture reset + persistent kernel once, on a private stream (the
+    // caller's stream may be the null stream, which cannot be captured).
+    if (p->ntasks > 0) {
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return fail(SPL_EHIP, "hipStreamCreateWithFlags failed");
+        }
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = launch_plan(p, cs);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            p->graph = g;
+            if (!rc && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
+            if (!rc) {
+                hipError_t e3 = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+                if (e3 != hipSuccess) rc = hip_fail(e3, "hipGraphInstantiate");
+            }
+        } else {
+            rc = hip_fail(e, "hipStreamBeginCapture");
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc) {
+            free_graph(p);
+            delete p;
+            return rc;
+        }
+    }
+    *out = p;
+    return SPL_OK;
+}
+
+int spline_plan_launch(const spline_plan_t* p, void* stream)
+{
+    if (!p) return fail(SPL_EINVAL, "plan is NULL");
+    if (p->ntasks == 0) return SPL_OK;
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(SPL_EINVAL, "current HIP device differs from the plan's device");
+    QS_HIP(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
+    return SPL_OK;
+}
+
+int spline_plan_launch_eager(const spline_plan_t* p, void* stream)
+{
+    if (!p) return fail(SPL_EINVAL, "plan is NULL");
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(SPL_EINVAL, "current HIP device differs from the plan's device");
+    return launch_plan(p, static_cast<hipStream_t>(stream));
+}
+
+int spline_plan_get_info(const spline_plan_t* p, spline_tile* tile, int32_t* n_tasks, int32_t* n_blocks)
+{
+    if (!p) return fail(SPL_EINVAL, "plan is NULL");
+    if (tile) *tile = p->tile;
+    if (n_tasks) *n_tasks = p->ntasks;
+    if (n_blocks) *n_blocks = p->nblocks;
+    return SPL_OK;
+}
+
+int spline_plan_destroy(spline_plan_t* p)
+{
+    if (!p) return SPL_OK;
+    free_graph(p);
+    delete p;
+    return SPL_OK;
+}
+
+}  // extern "C"

@@ -76,7 +76,7 @@ static int elem_bytes(spline_dtype s)
     return 0;
 }
 
-static bool mul_ok(int64_t a, int64_t b, int64_t* out)
+bool mul_ok(int64_t a, int64_t b, int64_t* out)
 {
     if (a < 0 || b < 0) return false;
     if (a != 0 && b > std::numeric_limits<int64_t>::max() / a) return false;
@@ -270,13 +270,13 @@ int spline_pack_host(const spline_grid* grid, int32_t n_orb, const double* coefs
 namespace qs {
 
 // A tile shape fits when whole tiles cover the padded row exactly.
-static bool tile_fits(const spline_s* s, const Variant& v)
+bool tile_fits(const spline_s* s, const Variant& v)
 {
     const int64_t tb = (int64_t)v.lpp * v.cw * 4 * v.nch;
     return v.store == s->store && s->layout.row_bytes % tb == 0;
 }
 
-static const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl)
+const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl)
 {
     int n = 0;
     const Variant* vs = variants(&n);
@@ -286,7 +286,7 @@ static const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bo
     return nullptr;
 }
 
-static int64_t tiles_of(const spline_s* s, const spline_tile& t)
+int64_t tiles_of(const spline_s* s, const spline_tile& t)
 {
     const int64_t tb = (int64_t)t.lpp * t.nch * t.cw * 4;
     return (s->layout.row_bytes + tb - 1) / tb;
@@ -332,7 +332,7 @@ static int check_tile(const spline_s* s, const spline_tile* t, bool vgl)
     return SPL_OK;
 }
 
-static EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G,
+EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G,
                           void* L)
 {
     EvalArgs a{};
