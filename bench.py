@@ -73,6 +73,78 @@ def time_steps(torch, fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / steps, wall
 
 
+MLP_FLOP_PER_POS = 2 * 5 * (96 * 256 + 256 * 256 + 256 * 192)
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def bench_mlp(args, q, W, torch, dev, np):
+    """The learned surrogate of the 48^3 / N=192 table: trained on the GPU
+    against the spline's VGL, then timed on the 256 x 192 batch with and
+    without the spline fallback, and its error measured against the spline
+    on held-out positions."""
+    log("bench: surrogate: building the 48^3 table and training %d steps ..." % args.mlp_steps)
+    grid, N, coefs, _ = W.make_table(5)
+    spl = q.Spline(grid, coefs, "f32", device=dev)
+    freqs, Ws, bs = W.mlp_init(5)
+    net = q.SurrogateMLP(N, freqs, q.flatten_mlp_params(Ws, bs), device=dev)
+    train = torch.from_numpy(W.mlp_samples(5, count=10 ** 6)).to(dev)
+    val = torch.from_numpy(W.mlp_samples(5, count=10 ** 5, validation=True)).to(dev)
+    bt = 4096
+    net.init_output(spl.eval_vgl(train[:bt]))
+    loss = torch.zeros(1, device=dev)
+    nb = train.shape[0] // bt
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.mlp_steps):
+        pos = train[(step % nb) * bt:(step % nb + 1) * bt]
+        lr = 2e-3 * 0.5 * (1.0 + np.cos(np.pi * step / args.mlp_steps)) + 2e-5
+        net.train_step(pos, spl.eval_vgl(pos), lr=lr, loss_out=loss if step == args.mlp_steps - 1 else None)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    net.build_error_map(spl, val[:8 * 8 * 8 * 64], bins_per_dim=8)
+
+    # error on held-out positions (the last 50000 validation points), against the spline
+    import oracle
+
+    hv = val[50000:]
+    ref = [t.cpu().numpy() for t in spl.eval_vgl(hv)]
+    e_net = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip(net.forward(hv), ref)]
+    Vf, Gf, Lf, nf = net.eval_vgl(hv, fallback=spl, tol=args.mlp_tol)
+    e_fb = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip((Vf, Gf, Lf), ref)]
+    frac_holdout = int(nf.cpu()[0]) / hv.shape[0]
+
+    # timing on the 256 walkers x 192 electrons batch
+    pos = torch.from_numpy(W.make_positions(5)).to(dev)
+    B = pos.shape[0]
+    out = net._out(B)
+    ms_net, _ = time_steps(torch, lambda: net.forward(pos, out=out), args.steps, args.warmup)
+    res = {}
+    ms_fb, _ = time_steps(torch, lambda: res.__setitem__("nf", net.eval_vgl(pos, fallback=spl, tol=args.mlp_tol,
+                                                                            out=out)[3]),
+                          args.steps, args.warmup)
+    frac = int(res["nf"].cpu()[0]) / B
+    sout = spl.alloc_outputs(B)
+    spl.autotune(pos, reps=2, out=sout)
+    ms_spl, _ = time_steps(torch, lambda: spl.eval_vgl(pos, out=sout), args.steps, args.warmup)
+    units = B * N
+    tflops = B * MLP_FLOP_PER_POS / (ms_net * 1e-3) / 1e12
+    return {
+        "table": "48^3 grid, N=192, FP32 (%.1f MB)" % (spl.layout.total_bytes / 1e6),
+        "network_bytes": int(net.layout.n_params * 2), "train_steps": args.mlp_steps, "train_batch": bt,
+        "train_seconds": train_s, "final_loss": float(loss.cpu()[0]),
+        "eps_network_only_vs_spline": {"V": e_net[0], "G": e_net[1], "L": e_net[2]},
+        "eps_with_fallback_vs_spline": {"V": e_fb[0], "G": e_fb[1], "L": e_fb[2]},
+        "tol": args.mlp_tol, "fallback_fraction_heldout": frac_holdout, "fallback_fraction_batch": frac,
+        "positions": B, "ms_network_only": ms_net, "ms_with_fallback": ms_fb, "ms_spline_f32": ms_spl,
+        "evals_per_s_network_only": units / (ms_net * 1e-3), "evals_per_s_with_fallback": units / (ms_fb * 1e-3),
+        "evals_per_s_spline_f32": units / (ms_spl * 1e-3),
+        "speedup_network_only_vs_spline": ms_spl / ms_net, "speedup_with_fallback_vs_spline": ms_spl / ms_fb,
+        "roofline_network_kernel": {"bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
+                                    "flop_per_position": MLP_FLOP_PER_POS},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +152,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 forms")
     ap.add_argument("--no-ragged", action="store_true", help="skip the four-table ragged plan")
+    ap.add_argument("--mlp-steps", type=int, default=3000, help="training steps of the surrogate (0 skips it)")
+    ap.add_argument("--mlp-tol", type=float, default=1e-3, help="error-map tolerance for the spline fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
@@ -207,6 +281,9 @@ def main() -> int:
         log("bench: ragged plan %.3f ms vs separate %.3f ms" % (ms_plan, ms_sep))
         del plan, sp, ps
         torch.cuda.empty_cache()
+
+    if args.mlp_steps > 0:
+        forms["mlp_surrogate"] = bench_mlp(args, q, W, torch, dev, np)
 
     cpu = None
     if not args.no_cpu_baseline:

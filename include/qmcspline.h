@@ -194,6 +194,100 @@ int spline_plan_get_info(const spline_plan_t* plan, spline_tile* tile, int32_t* 
 /* Releases the graph and the handle (not the workspace). NULL is accepted. */
 int spline_plan_destroy(spline_plan_t* plan);
 
+/* ---- Learned surrogate of a table ----------------------------------------
+ * A small periodic network replaces the table where it is accurate enough:
+ * features [sin 2pi k_j.u, cos 2pi k_j.u] (u = r / cell, 48 integer k_j),
+ * two hidden layers of 256 SiLU units, N outputs mapped to orbitals by a
+ * per-orbital affine map V = sd*y + mu.  V, G and L come from forward-mode
+ * derivatives (five streams: value, d/dx, d/dy, d/dz, Laplacian) through
+ * BF16 matrix-core products with FP32 accumulation.  It is trained on the
+ * GPU against the spline's own VGL (Sobolev loss, Adam), an empirical error
+ * map over spatial bins is built against the spline, and evaluation routes
+ * positions in bins whose error exceeds a tolerance back to the spline.  The
+ * paper has no network; the surrogate answers the memory-footprint question
+ * it raises (Sections 7.2, 8.2: the table is the largest read-only object). */
+typedef struct spline_mlp_s spline_mlp_t;
+
+/* Shape: n_freq = 48, width = {96, 256, 256, N} with N a multiple of 16 in
+ * [16, 256] (the compiled shape; other shapes give SPL_EUNSUPPORTED). */
+typedef struct {
+    int32_t n_freq;
+    int32_t width[4];
+} spline_mlp_desc;
+
+/* Byte offsets inside the parameter buffer (all 256-byte aligned), and the
+ * element offsets of each tensor inside the flat FP32 parameter vector
+ * [W1 (256x96) | b1 | W2 (256x256) | b2 | W3 (Nx256) | b3], weights stored
+ * [out][in].  The buffer is the whole network state: copying it is a
+ * checkpoint, and spline_mlp_attach resumes from one. */
+typedef struct {
+    int64_t n_params;
+    int64_t W1, b1, W2, b2, W3, b3;
+    int64_t params, adam_m, adam_v, weights_bf16, mu, sd, loss_w, freqs, bin_err, meta, total;
+    int32_t max_bins;
+} spline_mlp_layout;
+
+size_t spline_mlp_param_bytes(const spline_mlp_desc* desc);
+int spline_mlp_get_layout(const spline_mlp_desc* desc, spline_mlp_layout* out);
+
+/* New network in the caller's device buffer params_dev (>= param_bytes,
+ * 256-byte aligned): freqs_host [48][3] integer frequencies, cell[3] the
+ * orthorhombic cell, params_host the flat initial parameters (n_params
+ * FP32).  Adam moments start at zero, mu = 0, sd = 1, and every bin of the
+ * error map starts as untrusted.  Synchronises `stream`. */
+int spline_mlp_create(const spline_mlp_desc* desc, const int32_t* freqs_host, const double* cell,
+                      const float* params_host, void* params_dev, size_t bytes, void* stream, spline_mlp_t** out);
+
+/* Handle over an existing network state (a restored checkpoint). */
+int spline_mlp_attach(const spline_mlp_desc* desc, const double* cell, void* params_dev, size_t bytes, void* stream,
+                      spline_mlp_t** out);
+
+/* Sets mu, sd (per-orbital mean and standard deviation of V) and the loss
+ * weights (inverse variances of the normalised V, G, L) from a target batch
+ * V [B][N], G [B][3][N], L [B][N] on the device. */
+int spline_mlp_init_output(spline_mlp_t* mlp, const float* V, const float* G, const float* L, int64_t B,
+                           void* stream);
+
+/* Training.  Targets as above (the spline's VGL at pos [B][3]); ws: device
+ * workspace of spline_mlp_train_workspace_bytes(mlp, B) bytes.
+ * spline_mlp_grad writes the loss (device float) and the gradient of the
+ * Sobolev loss (device, n_params floats, flat layout) without updating;
+ * spline_mlp_train_step does one Adam step (beta 0.9/0.999, eps 1e-8) with
+ * learning rate lr and refreshes the BF16 weights. */
+size_t spline_mlp_train_workspace_bytes(const spline_mlp_t* mlp, int64_t B);
+int spline_mlp_grad(spline_mlp_t* mlp, const double* pos, const float* tV, const float* tG, const float* tL, int64_t B,
+                    void* ws, size_t ws_bytes, float* grad_out, float* loss_out, void* stream);
+int spline_mlp_train_step(spline_mlp_t* mlp, const double* pos, const float* tV, const float* tG, const float* tL,
+                          int64_t B, float lr, void* ws, size_t ws_bytes, float* loss_out, void* stream);
+
+/* Network-only VGL (no fallback) at pos [B][3]: V [B][N], G [B][3][N],
+ * L [B][N], FP32, device.  Asynchronous. */
+int spline_mlp_forward(const spline_mlp_t* mlp, const double* pos, int64_t B, float* V, float* G, float* L,
+                       void* stream);
+
+/* Error map: evaluates network and judge table (same N, same cell, FP32
+ * outputs) at n_val validation positions and stores, per spatial bin
+ * (bins_per_dim^3 bins, <= 16 per axis), the largest error over its points,
+ * orbitals and quantities, each relative to that orbital's largest |V|,
+ * |G_d| or |L| over all validation points.  Bins without points are
+ * untrusted.  The estimate is empirical, not a bound. */
+size_t spline_mlp_errmap_workspace_bytes(const spline_mlp_t* mlp, int64_t n_val);
+int spline_mlp_build_error_map(spline_mlp_t* mlp, const spline_t* judge, const double* val_pos, int64_t n_val,
+                               int32_t bins_per_dim, void* ws, size_t ws_bytes, void* stream);
+
+/* Evaluation with fallback: the network at every position, then the
+ * fallback table (may be NULL: network only) re-evaluates, in place, every
+ * position whose bin error exceeds tol (tol < 0 routes everything).
+ * n_fallback (device int32, may be NULL) receives the number routed.
+ * ws: device workspace of spline_mlp_eval_workspace_bytes(B) bytes. */
+size_t spline_mlp_eval_workspace_bytes(int64_t B);
+int spline_mlp_eval_vgl(const spline_mlp_t* mlp, const spline_t* fallback, float tol, const double* pos, int64_t B,
+                        float* V, float* G, float* L, void* ws, size_t ws_bytes, int32_t* n_fallback, void* stream);
+
+/* Adam steps taken and bins per axis of the current error map. */
+int spline_mlp_get_info(const spline_mlp_t* mlp, int64_t* step, int32_t* bins_per_dim);
+int spline_mlp_destroy(spline_mlp_t* mlp);
+
 /* Handle metadata queries. */
 int spline_get_info(const spline_t* s, spline_grid* grid, int32_t* n_orb, spline_dtype* store,
                     spline_layout* layout);

@@ -319,3 +319,213 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("n_freq", ctypes.c_int32), ("width", ctypes.c_int32 * 4)]
+
+
+class MlpLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_params", "W1", "b1", "W2", "b2", "W3", "b3", "params", "adam_m", "adam_v", "weights_bf16",
+                 "mu", "sd", "loss_w", "freqs", "bin_err", "meta", "total")] + [("max_bins", ctypes.c_int32)]
+
+
+_MLP_SIGS = {
+    "spline_mlp_param_bytes": (["p"], "sz"),
+    "spline_mlp_get_layout": (["p", "p"], "i"),
+    "spline_mlp_create": (["p", "p", "p", "p", "p", "sz", "p", "p"], "i"),
+    "spline_mlp_attach": (["p", "p", "p", "sz", "p", "p"], "i"),
+    "spline_mlp_init_output": (["p", "p", "p", "p", "i64", "p"], "i"),
+    "spline_mlp_train_workspace_bytes": (["p", "i64"], "sz"),
+    "spline_mlp_grad": (["p", "p", "p", "p", "p", "i64", "p", "sz", "p", "p", "p"], "i"),
+    "spline_mlp_train_step": (["p", "p", "p", "p", "p", "i64", "f", "p", "sz", "p", "p"], "i"),
+    "spline_mlp_forward": (["p", "p", "i64", "p", "p", "p", "p"], "i"),
+    "spline_mlp_errmap_workspace_bytes": (["p", "i64"], "sz"),
+    "spline_mlp_build_error_map": (["p", "p", "p", "i64", "i32", "p", "sz", "p"], "i"),
+    "spline_mlp_eval_workspace_bytes": (["i64"], "sz"),
+    "spline_mlp_eval_vgl": (["p", "p", "f", "p", "i64", "p", "p", "p", "p", "sz", "p", "p"], "i"),
+    "spline_mlp_get_info": (["p", "p", "p"], "i"),
+    "spline_mlp_destroy": (["p"], "i"),
+}
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_sigs", False):
+        T = {"p": ctypes.c_void_p, "sz": ctypes.c_size_t, "i": ctypes.c_int, "i32": ctypes.c_int32,
+             "i64": ctypes.c_int64, "f": ctypes.c_float}
+        for name, (args, res) in _MLP_SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = [T[a] for a in args]
+            fn.restype = T[res]
+        L._mlp_sigs = True
+    return L
+
+
+def mlp_desc(norb: int) -> MlpDesc:
+    d = MlpDesc()
+    d.n_freq = 48
+    for i, w in enumerate((96, 256, 256, int(norb))):
+        d.width[i] = w
+    return d
+
+
+def mlp_layout(norb: int) -> MlpLayout:
+    out = MlpLayout()
+    d = mlp_desc(norb)
+    check(_mlp_lib().spline_mlp_get_layout(ctypes.byref(d), ctypes.byref(out)))
+    return out
+
+
+def flatten_mlp_params(Ws, bs) -> np.ndarray:
+    """Flat FP32 parameter vector [W1 | b1 | W2 | b2 | W3 | b3] (weights [out][in])."""
+    parts = []
+    for W, b in zip(Ws, bs):
+        parts += [np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()]
+    return np.concatenate(parts)
+
+
+class SurrogateMLP:
+    """The learned surrogate of a table, state held in one device buffer."""
+
+    def __init__(self, norb: int, freqs=None, params=None, cell=(1.0, 1.0, 1.0), device="cuda", state=None,
+                 stream=None):
+        import torch
+
+        self._torch = torch
+        self.norb = int(norb)
+        self.cell = tuple(float(x) for x in cell)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        L = _mlp_lib()
+        self.desc = mlp_desc(norb)
+        self.layout = mlp_layout(norb)
+        nb = int(L.spline_mlp_param_bytes(ctypes.byref(self.desc)))
+        cell_a = (ctypes.c_double * 3)(*self.cell)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(torch, self.device, stream)
+            if state is not None:  # resume from a saved buffer
+                self.buf = state.to(self.device).clone()
+                if self.buf.numel() < nb:
+                    raise ValueError("state buffer too small")
+                check(L.spline_mlp_attach(ctypes.byref(self.desc), cell_a, ctypes.c_void_p(self.buf.data_ptr()),
+                                          self.buf.numel(), sp, ctypes.byref(h)))
+            else:
+                fr = np.ascontiguousarray(freqs, dtype=np.int32)
+                pr = np.ascontiguousarray(params, dtype=np.float32)
+                if fr.shape != (48, 3) or pr.size != self.layout.n_params:
+                    raise ValueError("need freqs [48,3] and %d parameters" % self.layout.n_params)
+                self.buf = torch.empty(nb, dtype=torch.uint8, device=self.device)
+                check(L.spline_mlp_create(ctypes.byref(self.desc), fr.ctypes.data, cell_a, pr.ctypes.data,
+                                          ctypes.c_void_p(self.buf.data_ptr()), nb, sp, ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def _stream(self, stream):
+        return _stream_ptr(self._torch, self.device, stream)[0]
+
+    def _workspace(self, key, nbytes):
+        t = self._ws.get(key)
+        if t is None or t.numel() < nbytes:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+            self._ws[key] = t
+        return t
+
+    def _out(self, B):
+        kw = dict(dtype=self._torch.float32, device=self.device)
+        return (self._torch.empty((B, self.norb), **kw), self._torch.empty((B, 3, self.norb), **kw),
+                self._torch.empty((B, self.norb), **kw))
+
+    @staticmethod
+    def _p(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def state(self):
+        """A copy of the whole network state (parameters, Adam moments, map)."""
+        return self.buf.clone()
+
+    def init_output(self, targets, stream=None):
+        V, G, L = targets
+        check(_mlp_lib().spline_mlp_init_output(self._h, self._p(V), self._p(G), self._p(L), V.shape[0],
+                                                self._stream(stream)))
+
+    def grad(self, pos, targets, stream=None):
+        B = pos.shape[0]
+        L_ = _mlp_lib()
+        nb = L_.spline_mlp_train_workspace_bytes(self._h, B)
+        ws = self._workspace("train", nb)
+        g = self._torch.empty(self.layout.n_params, dtype=self._torch.float32, device=self.device)
+        loss = self._torch.zeros(1, dtype=self._torch.float32, device=self.device)
+        V, G, L = targets
+        check(L_.spline_mlp_grad(self._h, self._p(pos), self._p(V), self._p(G), self._p(L), B, self._p(ws), ws.numel(),
+                                 self._p(g), self._p(loss), self._stream(stream)))
+        return g, loss
+
+    def train_step(self, pos, targets, lr: float, loss_out=None, stream=None):
+        B = pos.shape[0]
+        L_ = _mlp_lib()
+        nb = L_.spline_mlp_train_workspace_bytes(self._h, B)
+        ws = self._workspace("train", nb)
+        V, G, L = targets
+        check(L_.spline_mlp_train_step(self._h, self._p(pos), self._p(V), self._p(G), self._p(L), B, float(lr),
+                                       self._p(ws), ws.numel(),
+                                       None if loss_out is None else self._p(loss_out), self._stream(stream)))
+
+    def forward(self, pos, out=None, stream=None):
+        B = pos.shape[0]
+        V, G, L = out if out is not None else self._out(B)
+        check(_mlp_lib().spline_mlp_forward(self._h, self._p(pos), B, self._p(V), self._p(G), self._p(L),
+                                            self._stream(stream)))
+        return V, G, L
+
+    def build_error_map(self, judge, val_pos, bins_per_dim: int = 8, stream=None):
+        L_ = _mlp_lib()
+        n = val_pos.shape[0]
+        ws = self._workspace("errmap", L_.spline_mlp_errmap_workspace_bytes(self._h, n))
+        check(L_.spline_mlp_build_error_map(self._h, judge.handle, self._p(val_pos), n, int(bins_per_dim),
+                                            self._p(ws), ws.numel(), self._stream(stream)))
+
+    def eval_vgl(self, pos, fallback=None, tol: float = 1e-3, out=None, stream=None):
+        """(V, G, L, n_fallback tensor) with routing of untrusted bins to `fallback`."""
+        B = pos.shape[0]
+        L_ = _mlp_lib()
+        V, G, L = out if out is not None else self._out(B)
+        ws = self._workspace("eval", L_.spline_mlp_eval_workspace_bytes(B))
+        nf = self._torch.zeros(1, dtype=self._torch.int32, device=self.device)
+        check(L_.spline_mlp_eval_vgl(self._h, None if fallback is None else fallback.handle, float(tol),
+                                     self._p(pos), B, self._p(V), self._p(G), self._p(L), self._p(ws), ws.numel(),
+                                     self._p(nf), self._stream(stream)))
+        return V, G, L, nf
+
+    def info(self):
+        st, nb = ctypes.c_int64(), ctypes.c_int32()
+        check(_mlp_lib().spline_mlp_get_info(self._h, ctypes.byref(st), ctypes.byref(nb)))
+        return {"step": st.value, "bins_per_dim": nb.value}
+
+    def params_numpy(self):
+        """Parameters as float64 numpy arrays in the oracle's dictionary form."""
+        lay = self.layout
+        b = self.buf.cpu().numpy()
+        P = b[lay.params:lay.params + 4 * lay.n_params].view(np.float32).astype(np.float64)
+        H, N = 256, self.norb
+        out = dict(W1=P[lay.W1:lay.b1].reshape(H, 96), b1=P[lay.b1:lay.W2], W2=P[lay.W2:lay.b2].reshape(H, H),
+                   b2=P[lay.b2:lay.W3], W3=P[lay.W3:lay.b3].reshape(N, H), b3=P[lay.b3:lay.b3 + N])
+        out["mu"] = b[lay.mu:lay.mu + 4 * N].view(np.float32).astype(np.float64)
+        out["sd"] = b[lay.sd:lay.sd + 4 * N].view(np.float32).astype(np.float64)
+        out["freqs"] = b[lay.freqs:lay.freqs + 4 * 144].view(np.int32).reshape(48, 3).copy()
+        out["loss_w"] = b[lay.loss_w:lay.loss_w + 12].view(np.float32).astype(np.float64)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _mlp_lib().spline_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -40,6 +40,12 @@ struct EvalArgs {
     int32_t norb;
     int32_t tiles;      // orbital tiles per position
     int32_t pb;         // positions per workgroup
+    // Optional indirection (spline fallback of the surrogate): when idx is
+    // set, logical position i is row idx[i] of pos and of the outputs, and
+    // when nidx is set the number of logical positions is min(*nidx, B),
+    // read on the device.
+    const int32_t* idx;
+    const int32_t* nidx;
 };
 
 // One task of a multi-table plan: positions [first, first + count) of table

@@ -49,6 +49,7 @@ template <spline_dtype S> constexpr int vals_per_chunk(int cw)
 template <typename TA> struct alignas(16) PosW {
     TA w[3][9];
     int64_t off;  // byte offset of the stencil corner row (halo indices i0, i1, i2)
+    int64_t row;  // row of pos and of the outputs this position maps to
 };
 
 // Weights of one axis at offset t.  b: uniform cubic B-spline; the
@@ -94,8 +95,9 @@ __device__ inline void stage_position(const EvalArgs& a, int64_t b, PosW<TA>& w)
 {
     int i[3];
     double r[3];
+    const int64_t row = a.idx ? (int64_t)a.idx[b] : b;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) r[d] = a.pos[3 * b + d];  // all three loads in flight together
+    for (int d = 0; d < 3; ++d) r[d] = a.pos[3 * row + d];  // all three loads in flight together
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double t;
@@ -104,6 +106,7 @@ __device__ inline void stage_position(const EvalArgs& a, int64_t b, PosW<TA>& w)
         axis_weights<TA>((TA)t, (TA)g, (TA)(g * g), w.w[d]);
     }
     w.off = (int64_t)i[0] * a.xstride + (int64_t)i[1] * a.ystride + (int64_t)i[2] * a.row_bytes;
+    w.row = row;
 }
 
 template <typename T> __device__ inline T uniform(T x);
@@ -378,7 +381,7 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
             acc[4][v] = lxx[v] + lyz[v];
         }
 
-        const int64_t b = b0 + p;
+        const int64_t b = w.row;
         TA* Vo = reinterpret_cast<TA*>(a.V) + b * a.norb;
         TA* Gx = reinterpret_cast<TA*>(a.G) + (3 * b) * a.norb;
         TA* Gy = Gx + a.norb;
@@ -413,7 +416,13 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
     extern __shared__ unsigned char lds_raw[];
     PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
     const int64_t b0 = (int64_t)blockIdx.x * a.pb;
-    const int64_t rem = a.B - b0;
+    int64_t B = a.B;
+    if (a.nidx) {
+        const int64_t c = *a.nidx;
+        B = c < B ? c : B;
+    }
+    const int64_t rem = B - b0;
+    if (rem <= 0) return;  // whole workgroup beyond a device-side count
     const int np = rem < a.pb ? (int)rem : a.pb;
     eval_block<S, CW, NCH, LPP, VGL>(a, b0, np, W);
 }

@@ -1,0 +1,152 @@
+"""GPU tests of the learned surrogate (forward-mode MLP on matrix cores).
+
+- the fused forward kernel against the FP64 oracle with BF16 rounding of
+  every product operand emulated (tolerance 2^-7, per-orbital max-norm), and
+  against the exact FP64 network (reported);
+- the training gradient against the oracle's hand-written reverse pass
+  (FP64, no rounding): relative L2 error per tensor <= 5e-2 (BF16 operands);
+- training lowers the loss; the error map routes; routed positions equal the
+  spline bit for bit and the others equal the network bit for bit; routing
+  everything reproduces the spline exactly;
+- a saved state resumes with identical outputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def q(torch):
+    import paper_1708_02645_amd as qq
+    qq.lib()
+    return qq
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _net(q, N, seed=5):
+    freqs, Ws, bs = W.mlp_init(5, seed=seed, widths=(96, 256, 256, N))
+    return q.SurrogateMLP(N, freqs, q.flatten_mlp_params(Ws, bs)), freqs
+
+
+@pytest.fixture(scope="module")
+def small_table(q, torch):
+    rng = np.random.default_rng(31)
+    grid = (12, 12, 12)
+    G, a, b = W.planewave_params(rng, 192)
+    coefs = W.fit_planewave_coefs(grid, G, a, b)
+    return grid, coefs, q.Spline(grid, coefs, "f32")
+
+
+def test_forward_matches_oracle(torch, q, oracle, small_table):
+    grid, coefs, spl = small_table
+    net, _ = _net(q, 192)
+    pos_np = np.random.default_rng(1).random((1000 + 7, 3))
+    pos = torch.from_numpy(pos_np).cuda()
+    net.init_output(spl.eval_vgl(pos))
+    _say("case mlp forward")
+    got = [t.cpu().numpy() for t in net.forward(pos)]
+    p = net.params_numpy()
+    emu = M.forward(p, pos_np, bf16=True)
+    exact = M.forward(p, pos_np)
+    e_emu = [oracle.rel_err(g, r) for g, r in zip(got, emu)]
+    e_ex = [oracle.rel_err(g, r) for g, r in zip(got, exact)]
+    _say("mlp forward vs BF16-emulated oracle eps V/G/L = %.2e %.2e %.2e" % tuple(e_emu))
+    _say("mlp forward vs exact FP64 network eps V/G/L = %.2e %.2e %.2e" % tuple(e_ex))
+    assert max(e_emu) <= 2.0 ** -7
+
+
+def test_gradient_matches_oracle(torch, q, oracle, small_table):
+    grid, coefs, spl = small_table
+    net, _ = _net(q, 192, seed=6)
+    pos_np = np.random.default_rng(2).random((256, 3))
+    pos = torch.from_numpy(pos_np).cuda()
+    tgt = spl.eval_vgl(pos)
+    net.init_output(tgt)
+    _say("case mlp grad")
+    g, loss = net.grad(pos, tgt)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    p = net.params_numpy()
+    tV, tG, tL = (t.cpu().numpy().astype(np.float64) for t in tgt)
+    lval, gr = M.loss_and_grads(p, pos_np, tV, tG, tL, p["loss_w"])
+    lay = net.layout
+    _say("loss gpu %.6g oracle %.6g" % (float(loss.cpu()[0]), lval))
+    assert abs(float(loss.cpu()[0]) - lval) <= 2e-2 * lval
+    for name, lo, hi in (("W1", lay.W1, lay.b1), ("b1", lay.b1, lay.W2), ("W2", lay.W2, lay.b2),
+                         ("b2", lay.b2, lay.W3), ("W3", lay.W3, lay.b3), ("b3", lay.b3, lay.n_params)):
+        ref = gr[name].ravel()
+        err = np.linalg.norm(g[lo:hi] - ref) / np.linalg.norm(ref)
+        _say("grad %s rel L2 err %.3e" % (name, err))
+        assert err <= 5e-2, name
+
+
+def test_training_error_map_fallback_and_resume(torch, q, oracle, small_table):
+    grid, coefs, spl = small_table
+    net, _ = _net(q, 192, seed=7)
+    rng = np.random.default_rng(3)
+    train = torch.from_numpy(rng.random((4096 * 8, 3))).cuda()
+    val = torch.from_numpy(rng.random((8 * 8 * 8 * 16, 3))).cuda()
+    net.init_output(spl.eval_vgl(train[:4096]))
+    loss = torch.zeros(1, device="cuda")
+    losses = []
+    for step in range(300):
+        pos = train[(step % 8) * 4096:(step % 8 + 1) * 4096]
+        net.train_step(pos, spl.eval_vgl(pos), lr=1e-3 * (0.5 + 0.5 * np.cos(np.pi * step / 300)), loss_out=loss)
+        if step % 50 == 0 or step == 299:
+            losses.append(float(loss.cpu()[0]))
+    _say("case mlp training losses", ["%.3g" % x for x in losses])
+    assert losses[-1] < 0.5 * losses[0]
+    assert net.info()["step"] == 300
+
+    net.build_error_map(spl, val, bins_per_dim=8)
+    assert net.info()["bins_per_dim"] == 8
+    pos = torch.from_numpy(rng.random((5000, 3))).cuda()
+    ref = spl.eval_vgl(pos)
+    plain = net.forward(pos)
+    # tolerance below every bin error: everything is routed -> spline exactly
+    V, G, L, nf = net.eval_vgl(pos, fallback=spl, tol=-1.0)
+    torch.cuda.synchronize()
+    assert int(nf.cpu()[0]) == 5000
+    for a, b in zip((V, G, L), ref):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    # a tolerance between bin errors: routed rows equal the spline, the rest the network
+    errs = np.sort(net.buf[net.layout.bin_err:net.layout.bin_err + 4 * 512].cpu().numpy().view(np.float32))
+    tol = float(errs[len(errs) // 2])
+    V, G, L, nf = net.eval_vgl(pos, fallback=spl, tol=tol)
+    torch.cuda.synchronize()
+    n = int(nf.cpu()[0])
+    _say("mlp bins median error %.3e, routed %d of 5000" % (tol, n))
+    assert 0 < n < 5000
+    same_spl = np.all(V.cpu().numpy() == ref[0].cpu().numpy(), axis=1)
+    same_net = np.all(V.cpu().numpy() == plain[0].cpu().numpy(), axis=1)
+    assert (same_spl | same_net).all() and same_spl.sum() >= n
+    # no fallback table: network only
+    V2, _, _, _ = net.eval_vgl(pos, fallback=None)
+    np.testing.assert_array_equal(V2.cpu().numpy(), plain[0].cpu().numpy())
+
+    # resume from a saved state
+    st = net.state()
+    net2 = q.SurrogateMLP(192, state=st)
+    assert net2.info() == net.info()
+    for a, b in zip(net2.forward(pos), plain):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    net2.train_step(pos[:4096], spl.eval_vgl(pos[:4096]), lr=1e-4)
+    assert net2.info()["step"] == 301
