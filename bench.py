@@ -85,7 +85,8 @@ def bench_mlp(args, q, W, torch, dev, np):
     log("bench: surrogate: building the 48^3 table and training %d steps ..." % args.mlp_steps)
     grid, N, coefs, _ = W.make_table(5)
     spl = q.Spline(grid, coefs, "f32", device=dev)
-    freqs, Ws, bs = W.mlp_init(5)
+    _, Ws, bs = W.mlp_init(5)
+    freqs = q.spectral_frequencies(coefs)  # the 48 most energetic frequency pairs of the table
     net = q.SurrogateMLP(N, freqs, q.flatten_mlp_params(Ws, bs), device=dev)
     train = torch.from_numpy(W.mlp_samples(5, count=10 ** 6)).to(dev)
     val = torch.from_numpy(W.mlp_samples(5, count=10 ** 5, validation=True)).to(dev)
@@ -97,7 +98,7 @@ def bench_mlp(args, q, W, torch, dev, np):
     t0 = time.perf_counter()
     for step in range(args.mlp_steps):
         pos = train[(step % nb) * bt:(step % nb + 1) * bt]
-        lr = 2e-3 * 0.5 * (1.0 + np.cos(np.pi * step / args.mlp_steps)) + 2e-5
+        lr = 5e-3 * 0.5 * (1.0 + np.cos(np.pi * step / args.mlp_steps)) + 1e-5
         net.train_step(pos, spl.eval_vgl(pos), lr=lr, loss_out=loss if step == args.mlp_steps - 1 else None)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -152,7 +153,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 forms")
     ap.add_argument("--no-ragged", action="store_true", help="skip the four-table ragged plan")
-    ap.add_argument("--mlp-steps", type=int, default=3000, help="training steps of the surrogate (0 skips it)")
+    ap.add_argument("--mlp-steps", type=int, default=6000, help="training steps of the surrogate (0 skips it)")
     ap.add_argument("--mlp-tol", type=float, default=1e-3, help="error-map tolerance for the spline fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")

@@ -378,6 +378,35 @@ def mlp_layout(norb: int) -> MlpLayout:
     return out
 
 
+def spectral_frequencies(coefs: np.ndarray, count: int = 48, kmax: int = 4) -> np.ndarray:
+    """The `count` integer frequency vectors (one of each +-k pair, 0 < |k| <= kmax)
+    carrying the most energy in the table's coefficients, summed over orbitals.
+
+    Setup of the surrogate's features (not on the evaluation path): the
+    discrete Fourier transform of each orbital's coefficient grid, energy
+    |c_hat(k)|^2 + |c_hat(-k)|^2 per pair."""
+    c = np.asarray(coefs, dtype=np.float64)
+    n = c.shape[:3]
+    r = np.arange(-kmax, kmax + 1)
+    ks = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    ks = ks[((ks * ks).sum(1) <= kmax * kmax) & ((ks * ks).sum(1) > 0)]
+    energy = np.zeros(len(ks))
+    for m0 in range(0, c.shape[3], 32):
+        F = np.fft.fftn(c[..., m0:m0 + 32], axes=(0, 1, 2))
+        for i, k in enumerate(ks):
+            energy[i] += (np.abs(F[k[0] % n[0], k[1] % n[1], k[2] % n[2]]) ** 2).sum()
+    # keep one representative of each +-k pair (the lexicographically larger)
+    keep = [i for i, k in enumerate(ks) if tuple(k) > tuple(-k)]
+    pair_e = {tuple(ks[i]): energy[i] for i in keep}
+    for i, k in enumerate(ks):
+        if tuple(k) < tuple(-k):
+            pair_e[tuple(-k)] += energy[i]
+    order = sorted(pair_e, key=lambda k: (-pair_e[k], k))
+    if len(order) < count:
+        raise ValueError("fewer than %d frequency pairs with |k| <= %d" % (count, kmax))
+    return np.array(order[:count], dtype=np.int32)
+
+
 def flatten_mlp_params(Ws, bs) -> np.ndarray:
     """Flat FP32 parameter vector [W1 | b1 | W2 | b2 | W3 | b3] (weights [out][in])."""
     parts = []

@@ -228,21 +228,33 @@ static int compute_grad(spline_mlp_s* m, const double* pos, const float* tV, con
         QS_HIP(hipGetLastError());
         return SPL_OK;
     };
+    // bias gradients: column sums of the value-stream rows, in two stages
+    auto bgrad = [&](const float* dHl, int Wd, float* out) -> int {
+        constexpr int RB = 64;
+        hipLaunchKernelGGL(mlp_bias_grad_kernel, dim3((Wd + 63) / 64, RB), dim3(kThreads), 0, st, dHl, B, Wd, part);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid1(Wd)), dim3(kThreads), 0, st, part, RB, (int64_t)Wd,
+                           (int64_t)Wd, out);
+        QS_HIP(hipGetLastError());
+        return SPL_OK;
+    };
     rc = wgrad(dY, N, Z2, kHidden, grad + o.W3);
     if (rc < 0) return rc;
-    hipLaunchKernelGGL(mlp_bias_grad_kernel, dim3(grid1(N)), dim3(kThreads), 0, st, dY, B, N, grad + o.b3);
+    rc = bgrad(dY, N, grad + o.b3);
+    if (rc < 0) return rc;
     rc = gemm(dY, N, 1, P + o.W3, kHidden, 1, dZ, kHidden, nullptr, 0, R, kHidden, N, 1, 0, st);
     if (rc < 0) return rc;
     hipLaunchKernelGGL(mlp_act_bwd_kernel, dim3(grid1(B * kHidden)), dim3(kThreads), 0, st, H2, dZ, dH, B, kHidden);
     rc = wgrad(dH, kHidden, Z1, kHidden, grad + o.W2);
     if (rc < 0) return rc;
-    hipLaunchKernelGGL(mlp_bias_grad_kernel, dim3(grid1(kHidden)), dim3(kThreads), 0, st, dH, B, kHidden, grad + o.b2);
+    rc = bgrad(dH, kHidden, grad + o.b2);
+    if (rc < 0) return rc;
     rc = gemm(dH, kHidden, 1, P + o.W2, kHidden, 1, dZ, kHidden, nullptr, 0, R, kHidden, kHidden, 1, 0, st);
     if (rc < 0) return rc;
     hipLaunchKernelGGL(mlp_act_bwd_kernel, dim3(grid1(B * kHidden)), dim3(kThreads), 0, st, H1, dZ, dH, B, kHidden);
     rc = wgrad(dH, kHidden, X0, kIn, grad + o.W1);
     if (rc < 0) return rc;
-    hipLaunchKernelGGL(mlp_bias_grad_kernel, dim3(grid1(kHidden)), dim3(kThreads), 0, st, dH, B, kHidden, grad + o.b1);
+    rc = bgrad(dH, kHidden, grad + o.b1);
+    if (rc < 0) return rc;
     QS_HIP(hipGetLastError());
     return SPL_OK;
 }

@@ -39,8 +39,9 @@ __device__ inline void feature5(const int32_t* freqs, const double* u, const dou
     const int kx = freqs[3 * f], ky = freqs[3 * f + 1], kz = freqs[3 * f + 2];
     double x = (double)kx * u[0] + (double)ky * u[1] + (double)kz * u[2];
     x -= floor(x);
-    float s, c;
-    sincosf(kTwoPi * (float)x, &s, &c);
+    // hardware sine/cosine take the angle in revolutions: sin(2 pi x), x in [0, 1)
+    const float s = __builtin_amdgcn_sinf((float)x);
+    const float c = __builtin_amdgcn_cosf((float)x);
     const float gx = (float)(6.283185307179586 * kx / cell[0]);
     const float gy = (float)(6.283185307179586 * ky / cell[1]);
     const float gz = (float)(6.283185307179586 * kz / cell[2]);
@@ -71,13 +72,27 @@ __device__ inline int zoff(int s, int row, int col)
     return ((s * 16 + row) * kHidden + ((((col >> 3) ^ (row & 7)) << 3) | (col & 7)));
 }
 
-template <int KSTEPS>
-__device__ inline void hidden_layer(const bf16x8 (&A)[kStreams][KSTEPS], const __bf16* __restrict__ W,
-                                    const float* __restrict__ bias, __bf16* zb, int g, int c)
+// One layer on the matrix cores: ncg groups of 64 output columns (4 blocks
+// of 16), KSTEPS steps of 32 inputs, five streams.  The B operands (weights,
+// [out][in] rows of K BF16) of the next step are loaded while the current
+// step's products run, across group boundaries too.  `blocks` clamps the
+// column blocks of the last group (output layer); their results are unused.
+template <int KSTEPS, class Epi>
+__device__ inline void mfma_layer(const bf16x8 (&A)[kStreams][KSTEPS], const __bf16* __restrict__ W, int ncg,
+                                  int blocks, int g, int c, Epi&& epi)
 {
     constexpr int K = 32 * KSTEPS;
+    auto loadB = [&](int cg, int t, bf16x8 (&dst)[4]) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int blk = cg * 4 + nb < blocks ? cg * 4 + nb : blocks - 1;
+            dst[nb] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(blk * 16 + c) * K + 32 * t + 8 * g);
+        }
+    };
+    bf16x8 cur[4], nxt[4];
+    loadB(0, 0, cur);
 #pragma unroll 1
-    for (int cg = 0; cg < kHidden / 64; ++cg) {
+    for (int cg = 0; cg < ncg; ++cg) {
         f32x4 acc[kStreams][4];
 #pragma unroll
         for (int s = 0; s < kStreams; ++s)
@@ -85,16 +100,27 @@ __device__ inline void hidden_layer(const bf16x8 (&A)[kStreams][KSTEPS], const _
             for (int nb = 0; nb < 4; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < KSTEPS; ++t) {
-            bf16x8 wb[4];
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                wb[nb] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(cg * 64 + nb * 16 + c) * K + 32 * t + 8 * g);
+            if (t + 1 < KSTEPS) loadB(cg, t + 1, nxt);
+            else if (cg + 1 < ncg) loadB(cg + 1, 0, nxt);
 #pragma unroll
             for (int s = 0; s < kStreams; ++s)
 #pragma unroll
                 for (int nb = 0; nb < 4; ++nb)
-                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][t], wb[nb], acc[s][nb], 0, 0, 0);
+                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][t], cur[nb], acc[s][nb], 0, 0, 0);
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) cur[nb] = nxt[nb];
         }
+        epi(cg, acc);
+    }
+}
+
+// Hidden layer epilogue: bias, forward-mode SiLU, BF16 into the LDS tile.
+struct HiddenEpi {
+    const float* bias;
+    __bf16* zb;
+    int g, c;
+    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
+    {
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
             const int col = cg * 64 + nb * 16 + c;
@@ -114,7 +140,35 @@ __device__ inline void hidden_layer(const bf16x8 (&A)[kStreams][KSTEPS], const _
             }
         }
     }
-}
+};
+
+// Output epilogue: bias and the per-orbital affine map, stores to V, G, L.
+struct OutEpi {
+    const MlpFwdArgs* a;
+    const float* b3;
+    int64_t b0;
+    int blocks, g, c;
+    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
+    {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            if (cg * 4 + nb >= blocks) continue;
+            const int n = (cg * 4 + nb) * 16 + c;
+            const float sd = a->sd[n], mu = a->mu[n], bb = b3[n];
+            const int N = a->nout;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t b = b0 + 4 * g + j;
+                if (b >= a->B) continue;
+                a->V[b * N + n] = (acc[0][nb][j] + bb) * sd + mu;
+                a->G[(3 * b + 0) * N + n] = acc[1][nb][j] * sd;
+                a->G[(3 * b + 1) * N + n] = acc[2][nb][j] * sd;
+                a->G[(3 * b + 2) * N + n] = acc[3][nb][j] * sd;
+                a->L[b * N + n] = acc[4][nb][j] * sd;
+            }
+        }
+    }
+};
 
 __device__ inline void load_a(bf16x8 (&A)[kStreams][kHidden / 32], const __bf16* zb, int g, int c)
 {
@@ -149,57 +203,16 @@ __global__ __launch_bounds__(64) void mlp_vgl_kernel(MlpFwdArgs a)
             for (int s = 0; s < kStreams; ++s) A1[s][t][j] = (__bf16)f[s];
         }
 
-    hidden_layer<3>(A1, a.Wh + o.hW1, a.P + o.b1, zb, g, c);
+    mfma_layer<3>(A1, a.Wh + o.hW1, kHidden / 64, kHidden / 16, g, c, HiddenEpi{a.P + o.b1, zb, g, c});
     __syncthreads();
     bf16x8 A2[kStreams][kHidden / 32];
     load_a(A2, zb, g, c);
     __syncthreads();
-    hidden_layer<kHidden / 32>(A2, a.Wh + o.hW2, a.P + o.b2, zb, g, c);
+    mfma_layer<kHidden / 32>(A2, a.Wh + o.hW2, kHidden / 64, kHidden / 16, g, c, HiddenEpi{a.P + o.b2, zb, g, c});
     __syncthreads();
     load_a(A2, zb, g, c);
-
-    // Output layer: de-normalised V, G, L straight from the accumulators.
-    const __bf16* W3 = a.Wh + o.hW3;
-    const float* b3 = a.P + o.b3;
     const int nblk = a.nout / 16;
-#pragma unroll 1
-    for (int cg = 0; cg * 4 < nblk; ++cg) {
-        f32x4 acc[kStreams][4];
-#pragma unroll
-        for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < kHidden / 32; ++t) {
-            bf16x8 wb[4];
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const int blk = cg * 4 + nb < nblk ? cg * 4 + nb : nblk - 1;  // clamp; results discarded
-                wb[nb] = *reinterpret_cast<const bf16x8*>(W3 + (int64_t)(blk * 16 + c) * kHidden + 32 * t + 8 * g);
-            }
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-                for (int nb = 0; nb < 4; ++nb)
-                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[s][t], wb[nb], acc[s][nb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            if (cg * 4 + nb >= nblk) continue;
-            const int n = (cg * 4 + nb) * 16 + c;
-            const float sd = a.sd[n], mu = a.mu[n], bb = b3[n];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t b = b0 + 4 * g + j;
-                if (b >= a.B) continue;
-                a.V[b * a.nout + n] = (acc[0][nb][j] + bb) * sd + mu;
-                a.G[(3 * b + 0) * a.nout + n] = acc[1][nb][j] * sd;
-                a.G[(3 * b + 1) * a.nout + n] = acc[2][nb][j] * sd;
-                a.G[(3 * b + 2) * a.nout + n] = acc[3][nb][j] * sd;
-                a.L[b * a.nout + n] = acc[4][nb][j] * sd;
-            }
-        }
-    }
+    mfma_layer<kHidden / 32>(A2, a.Wh + o.hW3, (nblk + 3) / 4, nblk, g, c, OutEpi{&a, a.P + o.b3, b0, nblk, g, c});
 }
 
 // ---------------------------------------------------------------------------
@@ -354,14 +367,20 @@ __global__ void mlp_loss_kernel(const float* Y, const float* tV, const float* tG
     if (threadIdx.x == 0) atomicAdd(loss, red[0]);
 }
 
-// db[n] = sum over the value-stream rows of dH[b][n].
-__global__ void mlp_bias_grad_kernel(const float* dH, int64_t B, int W, float* db)
+// Column sums of the value-stream rows of dH [B][W], first stage: workgroup
+// (x, y) sums columns 64x..64x+63 over rows y, y + gridDim.y, ... into
+// part[y][W] (256 lanes: 64 columns x 4 row phases, combined in LDS).
+__global__ void mlp_bias_grad_kernel(const float* dH, int64_t B, int W, float* part)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= W) return;
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + cl;
     float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s += dH[b * W + n];
-    db[n] = s;
+    if (n < W)
+        for (int64_t b = (int64_t)blockIdx.y * 4 + rl; b < B; b += (int64_t)gridDim.y * 4) s += dH[b * W + n];
+    red[rl][cl] = s;
+    __syncthreads();
+    if (rl == 0 && n < W) part[(int64_t)blockIdx.y * W + n] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
 }
 
 __global__ void splitk_reduce_kernel(const float* part, int splits, int64_t count, int64_t stride, float* out)
