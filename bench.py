@@ -237,11 +237,27 @@ def main() -> int:
         return [oracle.rel_err(g, r) for g, r in zip(got, ref)]
 
     e32 = eps(out32)
+    # value only (the quadrature-point evaluation): same table and positions
+    ms_v, _ = time_steps(torch, lambda: s32.eval_v(pos, out=out32[0]), args.steps, args.warmup)
     del s32, out32
     torch.cuda.empty_cache()
 
+    # attainable read bandwidth: a plain streaming read of 4 GiB
+    rbuf = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+    rbuf.zero_()
+    best_read = 0.0
+    for grid_r in (1024, 2048):
+        scratch = torch.empty(grid_r * 256, dtype=torch.float32, device=dev)
+        ms_r, _ = time_steps(torch, lambda: q.probe_stream_read(rbuf, grid_r, out=scratch), 10, 2)
+        best_read = max(best_read, rbuf.numel() / (ms_r * 1e-3) / 1e9)
+    del rbuf
+    torch.cuda.empty_cache()
+
     forms = {"f32": {"evals_per_s": evals, "ms_per_step": ms32, "tile": list(tile32),
-                     "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]}}
+                     "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]},
+             "f32_value_only": {"evals_per_s": units / (ms_v * 1e-3), "ms_per_step": ms_v,
+                                "hbm_frac": units * (64 * 4 + 4) / (ms_v * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                "bytes_per_unit": 64 * 4 + 4}}
     if not args.no_forms:
         for dt in ("bf16", "f16"):
             s, out, t, ms, _ = bench_form(dt)
@@ -327,7 +343,9 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "bytes_per_unit": BYTES_PER_UNIT["f32"], "units_per_launch": units},
+                     "bytes_per_unit": BYTES_PER_UNIT["f32"], "units_per_launch": units,
+                     "attainable_stream_read_GBs": best_read,
+                     "frac_of_attainable": achieved / best_read if best_read > 0 else None},
         "cpu_baseline": cpu,
         "forms": forms,
         "wall_s_timed": wall32,

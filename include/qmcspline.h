@@ -288,6 +288,13 @@ int spline_mlp_eval_vgl(const spline_mlp_t* mlp, const spline_t* fallback, float
 int spline_mlp_get_info(const spline_mlp_t* mlp, int64_t* step, int32_t* bins_per_dim);
 int spline_mlp_destroy(spline_mlp_t* mlp);
 
+/* Measurement aid: one launch of a plain streaming-read kernel over `bytes`
+ * bytes of buf (device, 16-byte aligned; floor(bytes/16) float4 loads, 16
+ * bytes per lane, grid-stride), writing one float per thread to out (device,
+ * grid*256 floats).  Timing it gives the HBM rate a simple read attains, to
+ * set beside the published peak.  Asynchronous. */
+int spline_probe_stream_read(const void* buf, size_t bytes, float* out, int32_t grid, void* stream);
+
 /* Handle metadata queries. */
 int spline_get_info(const spline_t* s, spline_grid* grid, int32_t* n_orb, spline_dtype* store,
                     spline_layout* layout);

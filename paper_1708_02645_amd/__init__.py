@@ -75,6 +75,7 @@ def lib():
             "spline_plan_launch_eager": ([p, p], ctypes.c_int),
             "spline_plan_get_info": ([p, p, p, p], ctypes.c_int),
             "spline_plan_destroy": ([p], ctypes.c_int),
+            "spline_probe_stream_read": ([p, sz, p, i32, p], ctypes.c_int),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -124,6 +125,19 @@ def pack_host(grid, coefs: np.ndarray, dtype: str, cell=(1.0, 1.0, 1.0)) -> np.n
     g = make_grid(grid, cell)
     check(lib().spline_pack_host(ctypes.byref(g), norb, coefs.ctypes.data, DTYPES[dtype], buf.ctypes.data, nb))
     return buf
+
+
+def probe_stream_read(buf, grid: int = 1024, out=None, stream=None):
+    """One launch of the library's plain streaming-read kernel over a uint8
+    device tensor (for measuring the attainable read bandwidth)."""
+    import torch
+
+    if out is None:
+        out = torch.empty(grid * 256, dtype=torch.float32, device=buf.device)
+    sp, _ = _stream_ptr(torch, buf.device, stream)
+    check(lib().spline_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                         ctypes.c_void_p(out.data_ptr()), int(grid), sp))
+    return out
 
 
 def _stream_ptr(torch, device, stream):
