@@ -14,7 +14,6 @@
 namespace qs {
 
 // Declared in mlp_kernels.hip.
-__global__ void mlp_vgl_kernel(MlpFwdArgs a);
 __global__ void mlp_features_kernel(const double*, int64_t, const int32_t*, double, double, double, float*);
 __global__ void gemm_bf16_kernel(GemmArgs p);
 __global__ void mlp_act_fwd_kernel(const float*, float*, int64_t, int);
@@ -167,11 +166,7 @@ static int launch_forward(const spline_mlp_s* m, const double* pos, int64_t B, f
                           hipStream_t st)
 {
     if (B == 0) return SPL_OK;
-    const int64_t blocks = (B + 15) / 16;
-    if (blocks > 0x7fffffff) return fail(SPL_EINVAL, "batch too large");
-    hipLaunchKernelGGL(mlp_vgl_kernel, dim3((unsigned)blocks), dim3(64), 0, st, fwd_args(m, pos, B, V, G, L));
-    QS_HIP(hipGetLastError());
-    return SPL_OK;
+    return launch_mlp_forward(fwd_args(m, pos, B, V, G, L), st);
 }
 
 static int write_meta(spline_mlp_s* m, hipStream_t st)

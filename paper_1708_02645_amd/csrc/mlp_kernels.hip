@@ -1,219 +1,14 @@
-// Surrogate-network kernels for gfx950: the fused forward-mode evaluation
-// (matrix cores, BF16 operands, FP32 accumulation) and the training kernels
-// (features, generic BF16 matrix product, SiLU streams forward/backward,
-// Sobolev loss, gradient reductions, Adam), plus the error map and the
-// routing of positions to the spline fallback.
+// Surrogate-network training kernels for gfx950 (features, generic BF16
+// matrix product on the matrix cores, SiLU streams forward/backward, Sobolev
+// loss, gradient reductions, Adam), the error map and the routing of
+// positions to the spline fallback.  The fused evaluation kernel is in
+// mlp_forward.hip.
 #include "mlp_kernels.hpp"
 
 #include "common.hpp"
 
 namespace qs {
 
-constexpr float kTwoPi = 6.283185307179586f;
-
-// SiLU x*s and its first two derivatives, s = 1/(1 + e^-x).
-__device__ inline float silu3(float x, float& d1, float& d2)
-{
-    const float s = 1.0f / (1.0f + __expf(-x));
-    const float oms = 1.0f - s;
-    d1 = s * (1.0f + x * oms);
-    d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
-    return x * s;
-}
-
-__device__ inline float silu4(float x, float& d1, float& d2, float& d3)
-{
-    const float s = 1.0f / (1.0f + __expf(-x));
-    const float oms = 1.0f - s;
-    d1 = s * (1.0f + x * oms);
-    d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
-    d3 = s * oms * (3.0f * (1.0f - 2.0f * s) + x * (1.0f - 6.0f * s + 6.0f * s * s));
-    return x * s;
-}
-
-// One feature column k (0..2F-1) of one position, for the five streams:
-// sin(2 pi k.u) for k < F, cos for k >= F; u = r / cell.
-__device__ inline void feature5(const int32_t* freqs, const double* u, const double* cell, int k, float* out)
-{
-    const int f = k < kFreq ? k : k - kFreq;
-    const int kx = freqs[3 * f], ky = freqs[3 * f + 1], kz = freqs[3 * f + 2];
-    double x = (double)kx * u[0] + (double)ky * u[1] + (double)kz * u[2];
-    x -= floor(x);
-    // hardware sine/cosine take the angle in revolutions: sin(2 pi x), x in [0, 1)
-    const float s = __builtin_amdgcn_sinf((float)x);
-    const float c = __builtin_amdgcn_cosf((float)x);
-    const float gx = (float)(6.283185307179586 * kx / cell[0]);
-    const float gy = (float)(6.283185307179586 * ky / cell[1]);
-    const float gz = (float)(6.283185307179586 * kz / cell[2]);
-    const float g2 = gx * gx + gy * gy + gz * gz;
-    const float val = k < kFreq ? s : c;
-    const float dv = k < kFreq ? c : -s;
-    out[0] = val;
-    out[1] = dv * gx;
-    out[2] = dv * gy;
-    out[3] = dv * gz;
-    out[4] = -g2 * val;
-}
-
-// ---------------------------------------------------------------------------
-// Fused forward-mode evaluation: one wave evaluates 16 positions through all
-// layers.  Operand layout of v_mfma_f32_16x16x32_bf16 (lane l, g = l/16,
-// c = l%16): A[c][8g..8g+7], B[8g..8g+7][c], C[4g..4g+3][c].  Rows are the
-// 16 positions, one product per stream, so the five accumulators of a
-// (position, unit) pair sit in the same lane and slot and the SiLU streams
-// are combined in registers.  The layer input lives in registers (A
-// operands, all K); each layer's output is written once to LDS (a
-// [stream][16][256] BF16 tile with an XOR swizzle of 16-byte chunks) and read
-// back in A layout for the next layer.  Weights are read straight from
-// global memory (280 KB, L2-resident) as B operands.
-
-__device__ inline int zoff(int s, int row, int col)
-{
-    return ((s * 16 + row) * kHidden + ((((col >> 3) ^ (row & 7)) << 3) | (col & 7)));
-}
-
-// One layer on the matrix cores: ncg groups of 64 output columns (4 blocks
-// of 16), KSTEPS steps of 32 inputs, five streams.  The B operands (weights,
-// [out][in] rows of K BF16) of the next step are loaded while the current
-// step's products run, across group boundaries too.  `blocks` clamps the
-// column blocks of the last group (output layer); their results are unused.
-template <int KSTEPS, class Epi>
-__device__ inline void mfma_layer(const bf16x8 (&A)[kStreams][KSTEPS], const __bf16* __restrict__ W, int ncg,
-                                  int blocks, int g, int c, Epi&& epi)
-{
-    constexpr int K = 32 * KSTEPS;
-    auto loadB = [&](int cg, int t, bf16x8 (&dst)[4]) {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int blk = cg * 4 + nb < blocks ? cg * 4 + nb : blocks - 1;
-            dst[nb] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(blk * 16 + c) * K + 32 * t + 8 * g);
-        }
-    };
-    bf16x8 cur[4], nxt[4];
-    loadB(0, 0, cur);
-#pragma unroll 1
-    for (int cg = 0; cg < ncg; ++cg) {
-        f32x4 acc[kStreams][4];
-#pragma unroll
-        for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < KSTEPS; ++t) {
-            if (t + 1 < KSTEPS) loadB(cg, t + 1, nxt);
-            else if (cg + 1 < ncg) loadB(cg + 1, 0, nxt);
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-                for (int nb = 0; nb < 4; ++nb)
-                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][t], cur[nb], acc[s][nb], 0, 0, 0);
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) cur[nb] = nxt[nb];
-        }
-        epi(cg, acc);
-    }
-}
-
-// Hidden layer epilogue: bias, forward-mode SiLU, BF16 into the LDS tile.
-struct HiddenEpi {
-    const float* bias;
-    __bf16* zb;
-    int g, c;
-    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
-    {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int col = cg * 64 + nb * 16 + c;
-            const float b = bias[col];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 4 * g + j;
-                const float hv = acc[0][nb][j] + b;
-                const float hx = acc[1][nb][j], hy = acc[2][nb][j], hz = acc[3][nb][j], hl = acc[4][nb][j];
-                float d1, d2;
-                const float zv = silu3(hv, d1, d2);
-                zb[zoff(0, row, col)] = (__bf16)zv;
-                zb[zoff(1, row, col)] = (__bf16)(d1 * hx);
-                zb[zoff(2, row, col)] = (__bf16)(d1 * hy);
-                zb[zoff(3, row, col)] = (__bf16)(d1 * hz);
-                zb[zoff(4, row, col)] = (__bf16)(d1 * hl + d2 * (hx * hx + hy * hy + hz * hz));
-            }
-        }
-    }
-};
-
-// Output epilogue: bias and the per-orbital affine map, stores to V, G, L.
-struct OutEpi {
-    const MlpFwdArgs* a;
-    const float* b3;
-    int64_t b0;
-    int blocks, g, c;
-    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
-    {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            if (cg * 4 + nb >= blocks) continue;
-            const int n = (cg * 4 + nb) * 16 + c;
-            const float sd = a->sd[n], mu = a->mu[n], bb = b3[n];
-            const int N = a->nout;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t b = b0 + 4 * g + j;
-                if (b >= a->B) continue;
-                a->V[b * N + n] = (acc[0][nb][j] + bb) * sd + mu;
-                a->G[(3 * b + 0) * N + n] = acc[1][nb][j] * sd;
-                a->G[(3 * b + 1) * N + n] = acc[2][nb][j] * sd;
-                a->G[(3 * b + 2) * N + n] = acc[3][nb][j] * sd;
-                a->L[b * N + n] = acc[4][nb][j] * sd;
-            }
-        }
-    }
-};
-
-__device__ inline void load_a(bf16x8 (&A)[kStreams][kHidden / 32], const __bf16* zb, int g, int c)
-{
-#pragma unroll
-    for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-        for (int t = 0; t < kHidden / 32; ++t)
-            A[s][t] = *reinterpret_cast<const bf16x8*>(zb + zoff(s, c, 32 * t + 8 * g));
-}
-
-__global__ __launch_bounds__(64) void mlp_vgl_kernel(MlpFwdArgs a)
-{
-    __shared__ __attribute__((aligned(16))) __bf16 zb[kStreams * 16 * kHidden];
-    const int l = threadIdx.x, g = l >> 4, c = l & 15;
-    const int64_t b0 = (int64_t)blockIdx.x * 16;
-    const MlpOffsets o = mlp_offsets(a.nout);
-
-    // Layer-1 operands: the features of position b0 + c, in A layout.
-    int64_t bi = b0 + c;
-    if (bi >= a.B) bi = a.B - 1;  // ragged tail: computed, never stored
-    double u[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = a.pos[3 * bi + d] / a.cell[d];
-    bf16x8 A1[kStreams][3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            float f[5];
-            feature5(a.freqs, u, a.cell, 32 * t + 8 * g + j, f);
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s) A1[s][t][j] = (__bf16)f[s];
-        }
-
-    mfma_layer<3>(A1, a.Wh + o.hW1, kHidden / 64, kHidden / 16, g, c, HiddenEpi{a.P + o.b1, zb, g, c});
-    __syncthreads();
-    bf16x8 A2[kStreams][kHidden / 32];
-    load_a(A2, zb, g, c);
-    __syncthreads();
-    mfma_layer<kHidden / 32>(A2, a.Wh + o.hW2, kHidden / 64, kHidden / 16, g, c, HiddenEpi{a.P + o.b2, zb, g, c});
-    __syncthreads();
-    load_a(A2, zb, g, c);
-    const int nblk = a.nout / 16;
-    mfma_layer<kHidden / 32>(A2, a.Wh + o.hW3, (nblk + 3) / 4, nblk, g, c, OutEpi{&a, a.P + o.b3, b0, nblk, g, c});
-}
 
 // ---------------------------------------------------------------------------
 // Training kernels.  Stream-major activations: X[s][B][width], FP32.

@@ -78,4 +78,52 @@ struct GemmArgs {
     int64_t split_stride;
 };
 
+// Launches the fused evaluation kernel (mlp_forward.hip) on a.B positions.
+int launch_mlp_forward(const MlpFwdArgs& a, hipStream_t stream);
+
+// SiLU x*s and its first two (three) derivatives, s = 1/(1 + e^-x).
+__device__ inline float silu3(float x, float& d1, float& d2)
+{
+    const float s = 1.0f / (1.0f + __expf(-x));
+    const float oms = 1.0f - s;
+    d1 = s * (1.0f + x * oms);
+    d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
+    return x * s;
+}
+
+__device__ inline float silu4(float x, float& d1, float& d2, float& d3)
+{
+    const float s = 1.0f / (1.0f + __expf(-x));
+    const float oms = 1.0f - s;
+    d1 = s * (1.0f + x * oms);
+    d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
+    d3 = s * oms * (3.0f * (1.0f - 2.0f * s) + x * (1.0f - 6.0f * s + 6.0f * s * s));
+    return x * s;
+}
+
+// One feature column k (0..2F-1) of one position, for the five streams:
+// sin(2 pi k.u) for k < F, cos for k >= F; u = r / cell.  The phase k.u is
+// reduced modulo 1 in FP64; the hardware sine/cosine take the angle in
+// revolutions.
+__device__ inline void feature5(const int32_t* freqs, const double* u, const double* cell, int k, float* out)
+{
+    const int f = k < kFreq ? k : k - kFreq;
+    const int kx = freqs[3 * f], ky = freqs[3 * f + 1], kz = freqs[3 * f + 2];
+    double x = (double)kx * u[0] + (double)ky * u[1] + (double)kz * u[2];
+    x -= floor(x);
+    const float s = __builtin_amdgcn_sinf((float)x);
+    const float c = __builtin_amdgcn_cosf((float)x);
+    const float gx = (float)(6.283185307179586 * kx / cell[0]);
+    const float gy = (float)(6.283185307179586 * ky / cell[1]);
+    const float gz = (float)(6.283185307179586 * kz / cell[2]);
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    const float val = k < kFreq ? s : c;
+    const float dv = k < kFreq ? c : -s;
+    out[0] = val;
+    out[1] = dv * gx;
+    out[2] = dv * gy;
+    out[3] = dv * gz;
+    out[4] = -g2 * val;
+}
+
 }  // namespace qs
