@@ -1,0 +1,61 @@
+"""Determinant-ratio oracle (test infrastructure only; FP64).
+
+Section 3 of the paper: the Slater matrix is A(i, j) = phi_i(r_j).  Moving
+electron k from r_k to r'_k replaces column k of A by phi(r'_k); by the matrix
+determinant lemma the determinant changes by the factor
+
+    det A' / det A = sum_i Ainv(k, i) phi_i(r'_k),
+
+the dot product of row k of A^-1 with the orbital values at the new position.
+The gradient and the Laplacian of det A' with respect to r'_k, divided by
+det A, are the same dot product with the orbital gradients and Laplacians
+(the "derivatives" step of Algorithm 1), because det A' is linear in column k.
+
+Everything here is the plain definition: the orbital V, G, L from the FP64
+spline oracle, then one dot product per position with the given row.  Pinned
+in ``tests/test_oracle_det.py`` against determinants computed directly with
+``numpy.linalg`` (ratio) and against central differences of those
+determinants (gradient, Laplacian).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import eval_v, eval_vgl
+
+
+def slater_matrix(grid, coefs: np.ndarray, R: np.ndarray, cell=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """A[i, j] = phi_i(r_j) for the n = len(R) electrons of one walker (the
+    first n orbitals of the table)."""
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    n = R.shape[0]
+    V = eval_v(grid, coefs, R, cell)  # V[j, i] = phi_i(r_j)
+    return np.ascontiguousarray(V[:, :n].T)
+
+
+def ratio_vgl(grid, coefs: np.ndarray, pos: np.ndarray, rows: np.ndarray, cell=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """D[B, 5]: for position b and its row a = rows[b] (length N, the table's
+    orbital count), (sum a V, sum a Gx, sum a Gy, sum a Gz, sum a L)."""
+    V, G, L = eval_vgl(grid, coefs, pos, cell)
+    a = np.asarray(rows, dtype=np.float64).reshape(V.shape)
+    D = np.empty((V.shape[0], 5))
+    D[:, 0] = np.sum(a * V, axis=1)
+    for d in range(3):
+        D[:, 1 + d] = np.sum(a * G[:, d, :], axis=1)
+    D[:, 4] = np.sum(a * L, axis=1)
+    return D
+
+
+def ratio_v(grid, coefs: np.ndarray, pos: np.ndarray, rows: np.ndarray, cell=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """R[B]: sum_i rows[b, i] phi_i(pos_b)."""
+    V = eval_v(grid, coefs, pos, cell)
+    a = np.asarray(rows, dtype=np.float64).reshape(V.shape)
+    return np.sum(a * V, axis=1)
+
+
+def ratio_scale(rows: np.ndarray, Qref_max: np.ndarray) -> np.ndarray:
+    """sum_i |a_i| M_i per position: the size against which an error in a dot
+    product of a row with orbital quantities of per-orbital magnitude M_i is
+    measured (an error of e * M_i in every orbital moves the dot product by at
+    most e times this)."""
+    return np.abs(np.asarray(rows, dtype=np.float64)) @ np.asarray(Qref_max, dtype=np.float64)

@@ -1,0 +1,105 @@
+"""Pins of the determinant-ratio oracle (oracle/det.py).
+
+The oracle forms sum_i a_i Q_i(r') with a = row k of A^-1.  It is checked
+here against quantities it does not compute: determinants of the moved
+Slater matrix built from scratch and factorised by numpy.linalg (the ratio),
+and central differences of those determinants in the moved electron's
+coordinates (gradient and Laplacian).  Positions stay in the interior of
+their grid cells, where the spline is a cubic polynomial along each axis, so
+a second central difference is exact up to rounding and a first one is
+accurate to h^2 |f'''| / 6.  Using a column of A^-1 instead of a row, a
+dropped derivative stream or a wrong chain-rule factor fails these checks.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _interior(rng, count, grid, cell=(1.0, 1.0, 1.0), lo=0.25, hi=0.75):
+    g = np.asarray(grid)
+    idx = rng.integers(0, g, size=(count, 3))
+    t = rng.uniform(lo, hi, size=(count, 3))
+    return (idx + t) / g * np.asarray(cell)
+
+
+def _system(cell, seed):
+    grid, norb, coefs, _ = W.make_table(1)  # 16^3 grid, 32 orbitals, c ~ U[-1, 1]
+    rng = np.random.default_rng(seed)
+    R = _interior(rng, norb, grid, cell)
+    Rp = _interior(rng, norb, grid, cell)
+    return grid, norb, coefs, R, Rp
+
+
+def _moved_ratio(det, grid, coefs, R, k, r, cell, s0, l0):
+    R2 = R.copy()
+    R2[k] = r
+    s1, l1 = np.linalg.slogdet(det.slater_matrix(grid, coefs, R2, cell))
+    return s1 * s0 * np.exp(l1 - l0)
+
+
+CELLS = [(1.0, 1.0, 1.0), (1.0, 1.3, 0.8)]
+
+
+@pytest.mark.parametrize("cell", CELLS)
+def test_ratio_equals_determinant_ratio(oracle, cell):
+    from oracle import det
+
+    grid, n, coefs, R, Rp = _system(cell, 21)
+    A = det.slater_matrix(grid, coefs, R, cell)
+    assert np.linalg.cond(A) < 1e6
+    Ainv = np.linalg.inv(A)
+    s0, l0 = np.linalg.slogdet(A)
+    got = det.ratio_v(grid, coefs, Rp, Ainv, cell)  # position k uses row k
+    want = np.array([_moved_ratio(det, grid, coefs, R, k, Rp[k], cell, s0, l0) for k in range(n)])
+    phi = oracle.eval_v(grid, coefs, Rp, cell)
+    scale = np.sum(np.abs(Ainv) * np.abs(phi), axis=1)
+    assert np.max(np.abs(got - want) / scale) < 1e-9
+    # sensitivity: columns of A^-1 in place of rows give a different answer
+    wrong = det.ratio_v(grid, coefs, Rp, np.ascontiguousarray(Ainv.T), cell)
+    assert np.max(np.abs(wrong - want) / scale) > 1e-3
+    # the VGL variant's first entry is the same ratio
+    D = det.ratio_vgl(grid, coefs, Rp, Ainv, cell)
+    np.testing.assert_allclose(D[:, 0], got, rtol=1e-13, atol=1e-13 * scale.max())
+
+
+@pytest.mark.parametrize("cell", CELLS)
+def test_ratio_derivatives_are_determinant_derivatives(oracle, cell):
+    """grad det(A')/det A and lap det(A')/det A by central differences of the
+    moved determinant."""
+    from oracle import det
+
+    grid, n, coefs, R, Rp = _system(cell, 22)
+    A = det.slater_matrix(grid, coefs, R, cell)
+    Ainv = np.linalg.inv(A)
+    s0, l0 = np.linalg.slogdet(A)
+    D = det.ratio_vgl(grid, coefs, Rp, Ainv, cell)
+    _, G, L = oracle.eval_vgl(grid, coefs, Rp, cell)
+    gscale = np.abs(Ainv) @ np.abs(G).max(axis=(0, 1))
+    lscale = np.abs(Ainv) @ np.abs(L).max(axis=0)
+    h1, h2 = 1e-5, 1e-3  # every position is >= 0.0125 (a quarter grid spacing) from a knot
+    for k in range(0, n, 3):
+        f = lambda r: _moved_ratio(det, grid, coefs, R, k, r, cell, s0, l0)  # noqa: E731
+        f0 = f(Rp[k])
+        lap = 0.0
+        for d in range(3):
+            e = np.zeros(3)
+            e[d] = 1.0
+            g = (f(Rp[k] + h1 * e) - f(Rp[k] - h1 * e)) / (2 * h1)
+            assert abs(g - D[k, 1 + d]) < 1e-6 * gscale[k], (k, d, g, D[k, 1 + d])
+            lap += (f(Rp[k] + h2 * e) - 2 * f0 + f(Rp[k] - h2 * e)) / h2 ** 2
+        assert abs(lap - D[k, 4]) < 1e-8 * lscale[k], (k, lap, D[k, 4])
+
+
+def test_ratio_scale_bounds_perturbation(oracle):
+    """An error of e * M_i in orbital i moves the dot product by at most e
+    times ratio_scale."""
+    from oracle import det
+
+    rng = np.random.default_rng(5)
+    rows = rng.normal(size=(7, 11))
+    M = rng.uniform(0.5, 2.0, size=11)
+    s = det.ratio_scale(rows, M)
+    for _ in range(20):
+        err = rng.uniform(-1, 1, size=(7, 11)) * M * 1e-3
+        assert np.all(np.abs(np.sum(rows * err, axis=1)) <= 1e-3 * s * (1 + 1e-12))
