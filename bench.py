@@ -239,8 +239,34 @@ def main() -> int:
     e32 = eps(out32)
     # value only (the quadrature-point evaluation): same table and positions
     ms_v, _ = time_steps(torch, lambda: s32.eval_v(pos, out=out32[0]), args.steps, args.warmup)
-    del s32, out32
+    del out32
     torch.cuda.empty_cache()
+
+    # Fused determinant ratio: position b (walker-major, electron-minor) dots
+    # row b of the stacked inverse Slater matrices with its orbital V, G, L;
+    # only 5 (or 1) numbers per position are written.
+    log("bench: determinant-ratio forms ...")
+    rows_np = W.make_inverse_rows(3, B, N)
+    rows_d = torch.from_numpy(rows_np).to(dev)
+    Dbuf = torch.empty((B, 5), dtype=torch.float32, device=dev)
+    Rbuf = torch.empty((B,), dtype=torch.float32, device=dev)
+    ms_rvgl, _ = time_steps(torch, lambda: s32.eval_ratio_vgl(pos, rows_d, out=Dbuf), args.steps, args.warmup)
+    ms_rv, _ = time_steps(torch, lambda: s32.eval_ratio_v(pos, rows_d, out=Rbuf), args.steps, args.warmup)
+    from oracle import det as odet
+
+    ridx = idx[:64]
+    Dref = odet.ratio_vgl(grid, coefs, pos_np[ridx], rows_np[ridx])
+    Vr, Gr, Lr = oracle.eval_vgl(grid, coefs, pos_np[ridx])
+    Mq = [np.abs(Vr).max(0), np.abs(Gr).max((0, 1)), np.abs(Lr).max(0)]
+    sv, sg, sl = (odet.ratio_scale(rows_np[ridx], m) for m in Mq)
+    rscale = np.stack([sv, sg, sg, sg, sl], 1)
+    rit = torch.from_numpy(ridx).to(dev)
+    eps_ratio = float(np.max(np.abs(Dbuf[rit].double().cpu().numpy() - Dref) / rscale))
+    eps_ratio_v = float(np.max(np.abs(Rbuf[rit].double().cpu().numpy() - Dref[:, 0]) / sv))
+    del s32, rows_d, Dbuf, Rbuf, rows_np
+    torch.cuda.empty_cache()
+    bpu_rvgl = 64 * 4 + 4 + 20.0 / N
+    bpu_rv = 64 * 4 + 4 + 4.0 / N
 
     # attainable read bandwidth: a plain streaming read of 4 GiB
     rbuf = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
@@ -257,7 +283,14 @@ def main() -> int:
                      "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]},
              "f32_value_only": {"evals_per_s": units / (ms_v * 1e-3), "ms_per_step": ms_v,
                                 "hbm_frac": units * (64 * 4 + 4) / (ms_v * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                                "bytes_per_unit": 64 * 4 + 4}}
+                                "bytes_per_unit": 64 * 4 + 4},
+             "f32_ratio_vgl": {"evals_per_s": units / (ms_rvgl * 1e-3), "ms_per_step": ms_rvgl,
+                               "hbm_frac": units * bpu_rvgl / (ms_rvgl * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                               "bytes_per_unit": bpu_rvgl, "speedup_vs_f32_vgl": ms32 / ms_rvgl,
+                               "eps": eps_ratio},
+             "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv,
+                             "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                             "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}
     if not args.no_forms:
         for dt in ("bf16", "f16"):
             s, out, t, ms, _ = bench_form(dt)

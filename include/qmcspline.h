@@ -131,6 +131,41 @@ int spline_eval_vgl(const spline_t* s, const double* pos_dev, int64_t B, void* V
  * Section 3): V device [B][n_orb], same conventions as spline_eval_vgl. */
 int spline_eval_v(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* stream);
 
+/* Determinant ratio fused into the evaluation (Section 3: the ratio
+ * equation and the matrix determinant lemma).  With A(i,j) = phi_i(r_j),
+ * moving electron k to r'_k multiplies det A by sum_i Ainv(k,i) phi_i(r'_k),
+ * the dot product of row k of A^-1 with the orbital values at the new
+ * position; the same dot product with the orbital gradients and Laplacians
+ * gives grad det(A') / det(A) and lap det(A') / det(A) (the "derivatives"
+ * step of Algorithm 1).  The orbital values are consumed inside the kernel
+ * and never written.
+ *   pos_dev   device, [B][3] FP64 positions r' (conventions of spline_eval_vgl)
+ *   ainv_dev  device; the row for position b is the n_orb elements starting
+ *             at ainv_dev + (rows_dev ? rows_dev[b] : b) * ld, float (double
+ *             for an SPL_F64 table), aligned to the element size.  For a
+ *             sweep over all electrons of walkers stored as [walkers][n][n]
+ *             inverses, rows_dev = NULL and ld = n_orb; for one electron k of
+ *             every walker, ainv_dev = first inverse + k*n_orb, ld = n_orb^2;
+ *             for quadrature points sharing an electron, rows_dev maps each
+ *             point to its electron's row.  The rows must lie inside the
+ *             caller's buffer (not checked).
+ *   ld        elements between row indices 0 and 1 (>= 0)
+ *   D         device, [B][5] (ratio_vgl): sum_i a_i V_i, sum_i a_i Gx_i,
+ *             sum_i a_i Gy_i, sum_i a_i Gz_i, sum_i a_i L_i for the row a of
+ *             position b; D[b][0] is det A'/det A, D[b][1..3]/D[b][0] the
+ *             gradient of log det A' with respect to r', D[b][4]/D[b][0] its
+ *             lap det(A')/det(A').  R device, [B] (ratio_v): the ratio only,
+ *             for the quadrature points of the non-local pseudopotential.
+ * Outputs float (double for SPL_F64); per-position sums are added in a fixed
+ * order, so results are reproducible bit for bit for a given tile shape.
+ * The handle's VGL (value) tile shape is used.  Asynchronous on `stream`;
+ * B == 0 is a no-op.  SPL_EINVAL on NULL pointers, ld < 0 or misaligned
+ * rows; SPL_EUNSUPPORTED when no ratio kernel exists for the tile shape. */
+int spline_eval_ratio_vgl(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                          int64_t ld, const int32_t* rows_dev, void* D, void* stream);
+int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                        int64_t ld, const int32_t* rows_dev, void* R, void* stream);
+
 /* Tile shape control.  spline_tile_candidates lists the shapes valid for this
  * table (up to `cap`, count in *n); spline_set_tile validates and selects one. */
 int spline_tile_candidates(const spline_t* s, spline_tile* out, int32_t cap, int32_t* n);

@@ -62,6 +62,8 @@ def lib():
             "spline_create": ([p, i32, p, ctypes.c_int, p, sz, p, p], ctypes.c_int),
             "spline_eval_vgl": ([p, p, i64, p, p, p, p], ctypes.c_int),
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
+            "spline_eval_ratio_vgl": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
+            "spline_eval_ratio_v": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
             "spline_tile_candidates": ([p, p, i32, p], ctypes.c_int),
             "spline_set_tile": ([p, p], ctypes.c_int),
             "spline_get_tile": ([p, p], ctypes.c_int),
@@ -227,6 +229,50 @@ class Spline:
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_v(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()), sp))
         return V
+
+    def _ratio(self, vgl, pos, ainv, ld, rows, out, stream):
+        torch = self._torch
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        if not (isinstance(ainv, torch.Tensor) and ainv.device == self.device and ainv.dtype == self.out_dtype
+                and ainv.is_contiguous()):
+            raise ValueError("ainv must be a contiguous %s tensor on %s" % (self.out_dtype, self.device))
+        ld = self.norb if ld is None else int(ld)
+        if ld < 0:
+            raise ValueError("ld must be >= 0")
+        if rows is not None:
+            if not (isinstance(rows, torch.Tensor) and rows.dtype == torch.int32 and rows.device == self.device
+                    and rows.is_contiguous() and tuple(rows.shape) == (B,)):
+                raise ValueError("rows must be a contiguous int32 [B] tensor on %s" % self.device)
+            last = int(rows.max().item()) if B else 0
+            if B and int(rows.min().item()) < 0:
+                raise ValueError("negative row index")
+        else:
+            last = B - 1
+        if B and last * ld + self.norb > ainv.numel():
+            raise ValueError("rows of ainv extend past the tensor")
+        shape = (B, 5) if vgl else (B,)
+        D = out if out is not None else torch.empty(shape, dtype=self.out_dtype, device=self.device)
+        if tuple(D.shape) != shape or D.dtype != self.out_dtype or not D.is_contiguous() or D.device != self.device:
+            raise ValueError("output tensor must be a contiguous %s %s tensor" % (self.out_dtype, shape))
+        fn = lib().spline_eval_ratio_vgl if vgl else lib().spline_eval_ratio_v
+        with torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(torch, self.device, stream)
+            check(fn(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(ainv.data_ptr()), ld,
+                     ctypes.c_void_p(rows.data_ptr()) if rows is not None else None, ctypes.c_void_p(D.data_ptr()),
+                     sp))
+        return D
+
+    def eval_ratio_vgl(self, pos, ainv, ld=None, rows=None, out=None, stream=None):
+        """D[B,5]: dot products of each position's row of A^-1 with the orbital
+        value, gradient (x, y, z) and Laplacian at that position (determinant
+        lemma).  The row of position b starts at element (rows[b] or b) * ld of
+        ainv (ld defaults to the orbital count)."""
+        return self._ratio(True, pos, ainv, ld, rows, out, stream)
+
+    def eval_ratio_v(self, pos, ainv, ld=None, rows=None, out=None, stream=None):
+        """R[B]: determinant ratios only (dot products with orbital values)."""
+        return self._ratio(False, pos, ainv, ld, rows, out, stream)
 
     def tile_candidates(self):
         n = ctypes.c_int32()

@@ -46,6 +46,11 @@ struct EvalArgs {
     // read on the device.
     const int32_t* idx;
     const int32_t* nidx;
+    // Determinant-ratio launches: row of A^-1 for logical row r starts at
+    // ainv + (arows ? arows[r] : r) * ald elements; the sums go to V.
+    const void* ainv;
+    int64_t ald;
+    const int32_t* arows;
 };
 
 // One task of a multi-table plan: positions [first, first + count) of table
@@ -69,13 +74,23 @@ struct Variant {
     spline_dtype store;
     int cw, nch, lpp;
     bool vgl;              // true: V, G, L; false: value only
+    bool ratio;            // determinant-ratio epilogue instead of stores
     const void* fn;        // __global__ function symbol (single table)
     const void* plan_fn;   // persistent multi-table kernel (VGL variants only), else null
-    size_t lds_per_pos;
+    size_t lds_per_pos;    // staged weights per position
+    size_t lds_per_tile;   // ratio partial sums per (position, tile), else 0
 };
 
 // Registry of every compiled variant (filled by the kernel files).
 const Variant* variants(int* count);
+
+// LDS bytes of a launch of v with pb positions per workgroup and `tiles`
+// orbital tiles per position.
+inline size_t launch_lds(const Variant& v, int pb, int64_t tiles)
+{
+    return (size_t)pb * (v.lds_per_pos + (size_t)tiles * v.lds_per_tile);
+}
+constexpr size_t kMaxLds = 64 * 1024;
 
 // Launch one variant; validates nothing (the caller did).
 int launch(const Variant& v, const EvalArgs& a, hipStream_t stream);
@@ -91,7 +106,7 @@ namespace qs {
 bool mul_ok(int64_t a, int64_t b, int64_t* out);
 // Whole tiles of variant v cover the padded rows of table s exactly.
 bool tile_fits(const spline_s* s, const Variant& v);
-const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl);
+const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl, bool ratio = false);
 int64_t tiles_of(const spline_s* s, const spline_tile& t);
 EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G,
                    void* L);

@@ -1,38 +1,8 @@
-// Compiled tile shapes of the evaluation kernels for F16 tables (generated list;
-// edit here and in the registry together).
-#include "eval_kernel.hpp"
+// Store and value-only evaluation kernels for SPL_F16 tables, one per tile shape.
+#include "shapes.hpp"
 
 namespace qs {
 
-#define QS_VARIANT(CW, NCH, LPP)                                                          \
-    {SPL_F16, CW, NCH, LPP, true, (const void*)&eval_kernel<SPL_F16, CW, NCH, LPP, true>,          \
-     (const void*)&plan_kernel<SPL_F16, CW, NCH, LPP>, sizeof(PosW<Acc<SPL_F16>::type>)},            \
-    {SPL_F16, CW, NCH, LPP, false, (const void*)&eval_kernel<SPL_F16, CW, NCH, LPP, false>,        \
-     nullptr, sizeof(PosW<Acc<SPL_F16>::type>)},
-
-static const Variant k_variants[] = {
-    QS_VARIANT(1, 1, 64)
-    QS_VARIANT(1, 2, 64)
-    QS_VARIANT(1, 3, 64)
-    QS_VARIANT(2, 1, 64)
-    QS_VARIANT(2, 2, 64)
-    QS_VARIANT(2, 3, 64)
-    QS_VARIANT(3, 1, 64)
-    QS_VARIANT(3, 2, 64)
-    QS_VARIANT(4, 1, 64)
-    QS_VARIANT(2, 1, 32)
-    QS_VARIANT(3, 1, 32)
-    QS_VARIANT(4, 1, 32)
-    QS_VARIANT(4, 2, 32)
-    QS_VARIANT(2, 1, 16)
-    QS_VARIANT(4, 1, 16)
-    QS_VARIANT(4, 2, 16)
-};
-
-const Variant* variants_f16(int* count)
-{
-    *count = (int)(sizeof(k_variants) / sizeof(k_variants[0]));
-    return k_variants;
-}
+QS_REGISTRY(variants_f16, QS_SHAPES_16, QS_EVAL_VARIANTS, SPL_F16)
 
 }  // namespace qs

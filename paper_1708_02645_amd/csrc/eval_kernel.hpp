@@ -200,10 +200,37 @@ __device__ inline void store_vals(TA* dst, const TA* v, int o, int norb, bool al
     }
 }
 
+// Load VPC consecutive values of a caller row, zero beyond norb: one
+// naturally aligned vector load when `aligned` and inside the row.
+template <typename TA, int VPC>
+__device__ inline void load_vals(const TA* src, TA* v, int o, int norb, bool aligned)
+{
+    if (aligned && o + VPC <= norb) {
+        const Pack<TA, VPC> p = *reinterpret_cast<const Pack<TA, VPC>*>(src + o);
+#pragma unroll
+        for (int i = 0; i < VPC; ++i) v[i] = p.v[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VPC; ++i) v[i] = o + i < norb ? src[o + i] : TA(0);
+    }
+}
+
 // Evaluates positions [b0, b0 + np) of one table with the whole workgroup.
-// W: LDS staging for at least np positions.  Contains one workgroup barrier
-// (between staging and evaluation); callers that reuse W must barrier again.
-template <spline_dtype S, int CW, int NCH, int LPP, bool VGL>
+// W: LDS staging for at least a.pb positions.  Contains one workgroup barrier
+// (between staging and evaluation), two with RATIO; callers that reuse W must
+// barrier again.
+//
+// RATIO: instead of storing the orbital values, dot them with the caller's
+// row of the inverse Slater matrix (the determinant lemma: the ratio of the
+// determinants after and before moving one electron is the dot product of
+// that electron's row of A^-1 with the orbital values at the new position,
+// and the same dot product with gradients and Laplacians gives the
+// derivatives).  Each lane forms its partial sums in registers, the LPP lanes
+// of a group combine them by a butterfly of cross-lane exchanges, and the
+// per-tile sums of a position are added in tile order after a barrier, so
+// the result does not depend on which group took which tile.  NQ = 5 (VGL)
+// or 1 (value) sums per position are written to a.V[row][NQ].
+template <spline_dtype S, int CW, int NCH, int LPP, bool VGL, bool RATIO = false>
 __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<typename Acc<S>::type>* W)
 {
     using TA = typename Acc<S>::type;
@@ -224,6 +251,12 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
     const int lane = tid % LPP;
     const int items = np * a.tiles;
     const uint32_t loff = (uint32_t)lane * CHB;
+    constexpr int NQ = VGL ? 5 : 1;
+    // RATIO: per-(position, tile) sums, in LDS after the staged weights.
+    TA* part = reinterpret_cast<TA*>(W + a.pb);
+    bool row_aligned = false;
+    if constexpr (RATIO)
+        row_aligned = a.ald % VPC == 0 && (uintptr_t)a.ainv % alignof(Pack<TA, VPC>) == 0;
 
     for (int it = g; it < items; it += groups) {
         const int item = (LPP == 64) ? uniform<int>(it) : it;
@@ -382,6 +415,37 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
         }
 
         const int64_t b = w.row;
+        if constexpr (RATIO) {
+            const int64_t arow = a.arows ? (int64_t)a.arows[b] : b;
+            const TA* ar = reinterpret_cast<const TA*>(a.ainv) + arow * a.ald;
+            TA sum[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sum[q] = TA(0);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int o = tile * TO + c * LPP * VPC + lane * VPC;
+                TA av[VPC];
+                load_vals<TA, VPC>(ar, av, o, a.norb, row_aligned);
+                if constexpr (S == SPL_BF16 || S == SPL_F16) {
+                    // power-of-two scales: a*(s*x) == (a*s)*x exactly
+#pragma unroll
+                    for (int i = 0; i < VPC; ++i) av[i] *= a.scales[o + i];
+                }
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                    for (int i = 0; i < VPC; ++i) sum[q] = fma(av[i], acc[q][c * VPC + i], sum[q]);
+            }
+#pragma unroll
+            for (int m = LPP / 2; m >= 1; m >>= 1)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) sum[q] += __shfl_xor(sum[q], m, LPP);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) part[(p * a.tiles + tile) * NQ + q] = sum[q];
+            }
+            continue;
+        }
         TA* Vo = reinterpret_cast<TA*>(a.V) + b * a.norb;
         TA* Gx = reinterpret_cast<TA*>(a.G) + (3 * b) * a.norb;
         TA* Gy = Gx + a.norb;
@@ -406,10 +470,24 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
             for (int q = 0; q < (VGL ? 5 : 1); ++q) store_vals<TA, VPC>(r[q], &acc[q][c * VPC], o, a.norb, aligned);
         }
     }
+    if constexpr (RATIO) {
+        __syncthreads();
+        for (int p = tid; p < np; p += kBlock) {
+            TA sum[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sum[q] = part[p * a.tiles * NQ + q];
+            for (int t = 1; t < a.tiles; ++t)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) sum[q] += part[(p * a.tiles + t) * NQ + q];
+            TA* D = reinterpret_cast<TA*>(a.V) + W[p].row * NQ;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) D[q] = sum[q];
+        }
+    }
 }
 
 // One table: workgroup i takes positions [i*pb, i*pb + pb).
-template <spline_dtype S, int CW, int NCH, int LPP, bool VGL>
+template <spline_dtype S, int CW, int NCH, int LPP, bool VGL, bool RATIO = false>
 __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
 {
     using TA = typename Acc<S>::type;
@@ -424,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
     const int64_t rem = B - b0;
     if (rem <= 0) return;  // whole workgroup beyond a device-side count
     const int np = rem < a.pb ? (int)rem : a.pb;
-    eval_block<S, CW, NCH, LPP, VGL>(a, b0, np, W);
+    eval_block<S, CW, NCH, LPP, VGL, RATIO>(a, b0, np, W);
 }
 
 // Several tables in one launch (ragged batches): a persistent grid pops

@@ -37,12 +37,17 @@ const Variant* variants_f32(int*);
 const Variant* variants_f64(int*);
 const Variant* variants_bf16(int*);
 const Variant* variants_f16(int*);
+const Variant* ratio_variants_f32(int*);
+const Variant* ratio_variants_f64(int*);
+const Variant* ratio_variants_bf16(int*);
+const Variant* ratio_variants_f16(int*);
 
 const Variant* variants(int* count)
 {
     static std::vector<Variant> all;
     if (all.empty()) {
-        for (auto f : {variants_f64, variants_f32, variants_bf16, variants_f16}) {
+        for (auto f : {variants_f64, variants_f32, variants_bf16, variants_f16, ratio_variants_f64,
+                       ratio_variants_f32, ratio_variants_bf16, ratio_variants_f16}) {
             int n = 0;
             const Variant* v = f(&n);
             all.insert(all.end(), v, v + n);
@@ -59,7 +64,7 @@ int launch(const Variant& v, const EvalArgs& a, hipStream_t stream)
         return fail(SPL_EINVAL, "batch too large for one launch");
     EvalArgs args = a;
     void* params[] = {&args};
-    const size_t lds = v.lds_per_pos * (size_t)a.pb;
+    const size_t lds = launch_lds(v, a.pb, a.tiles);
     QS_HIP(hipLaunchKernel(v.fn, dim3((unsigned)blocks), dim3(kBlock), params, lds, stream));
     QS_HIP(hipGetLastError());
     return SPL_OK;
@@ -276,12 +281,13 @@ bool tile_fits(const spline_s* s, const Variant& v)
     return v.store == s->store && s->layout.row_bytes % tb == 0;
 }
 
-const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl)
+const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl, bool ratio)
 {
     int n = 0;
     const Variant* vs = variants(&n);
     for (int i = 0; i < n; ++i)
-        if (vs[i].store == st && vs[i].cw == cw && vs[i].nch == nch && vs[i].lpp == lpp && vs[i].vgl == vgl)
+        if (vs[i].store == st && vs[i].cw == cw && vs[i].nch == nch && vs[i].lpp == lpp && vs[i].vgl == vgl &&
+            vs[i].ratio == ratio)
             return &vs[i];
     return nullptr;
 }
@@ -302,7 +308,7 @@ static spline_tile default_tile(const spline_s* s, bool vgl)
     double best_score = 1e300;
     for (int i = 0; i < n; ++i) {
         const Variant& v = vs[i];
-        if (v.vgl != vgl || !tile_fits(s, v)) continue;
+        if (v.vgl != vgl || v.ratio || !tile_fits(s, v)) continue;
         const int words = v.cw * v.nch;
         if (words > 6) continue;
         spline_tile t{v.cw, v.nch, v.lpp, 32};
@@ -452,6 +458,50 @@ int spline_eval_v(const spline_t* s, const double* pos_dev, int64_t B, void* V, 
     return eval_common(s, pos_dev, B, V, nullptr, nullptr, stream, false);
 }
 
+// Determinant-ratio launches use the table's VGL (value) tile shape; the
+// positions per workgroup are halved until the per-tile partial sums fit in
+// LDS next to the staged weights.
+static int ratio_common(const spline_t* s, const double* pos, int64_t B, const void* ainv, int64_t ld,
+                        const int32_t* rows, void* D, void* stream, bool vgl)
+{
+    if (!s) return fail(SPL_EINVAL, "handle is NULL");
+    if (B < 0) return fail(SPL_EINVAL, "B must be >= 0");
+    if (ld < 0) return fail(SPL_EINVAL, "ld must be >= 0");
+    if (B == 0) return SPL_OK;
+    if (!pos || !ainv || !D) return fail(SPL_EINVAL, "NULL position, inverse-row or output pointer");
+    const uintptr_t eb = s->store == SPL_F64 ? 8 : 4;
+    if ((uintptr_t)ainv % eb || (uintptr_t)D % eb)
+        return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
+    int64_t tmp;
+    if (!mul_ok(B, 5 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    spline_tile t = vgl ? s->tile : s->vtile;
+    const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
+    if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");
+    const int64_t tiles = tiles_of(s, t);
+    while (t.pb > 1 && launch_lds(*v, t.pb, tiles) > kMaxLds) t.pb /= 2;
+    if (launch_lds(*v, t.pb, tiles) > kMaxLds) return fail(SPL_EUNSUPPORTED, "row too wide for the partial sums");
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev != s->device) return fail(SPL_EINVAL, "current HIP device differs from the table's device");
+    EvalArgs a = make_args(s, t, pos, B, D, nullptr, nullptr);
+    a.ainv = ainv;
+    a.ald = ld;
+    a.arows = rows;
+    return launch(*v, a, static_cast<hipStream_t>(stream));
+}
+
+int spline_eval_ratio_vgl(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev, int64_t ld,
+                          const int32_t* rows_dev, void* D, void* stream)
+{
+    return ratio_common(s, pos_dev, B, ainv_dev, ld, rows_dev, D, stream, true);
+}
+
+int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev, int64_t ld,
+                        const int32_t* rows_dev, void* R, void* stream)
+{
+    return ratio_common(s, pos_dev, B, ainv_dev, ld, rows_dev, R, stream, false);
+}
+
 int spline_tile_candidates(const spline_t* s, spline_tile* out, int32_t cap, int32_t* n)
 {
     if (!s || !n) return fail(SPL_EINVAL, "NULL argument");
@@ -461,7 +511,7 @@ int spline_tile_candidates(const spline_t* s, spline_tile* out, int32_t cap, int
     int32_t k = 0;
     for (int i = 0; i < nv; ++i) {
         const Variant& v = vs[i];
-        if (!v.vgl || !tile_fits(s, v)) continue;
+        if (!v.vgl || v.ratio || !tile_fits(s, v)) continue;
         for (int pb : {16, 32, 64}) {
             if (v.lds_per_pos * (size_t)pb > 64 * 1024) continue;
             if (k < cap) out[k] = spline_tile{v.cw, v.nch, v.lpp, pb};

@@ -140,3 +140,11 @@ def test_pack_f16_ties_and_extremes(oracle):
         vals, sc, L = _unpack(buf, (1, 1, 1), 4, dt)
         dq, _ = oracle.dequantize(c, dt)
         np.testing.assert_array_equal(vals[1, 1, 1, :4] * sc[:4], dq[0, 0, 0])
+
+
+def test_ratio_entry_points_reject_bad_arguments_without_a_gpu():
+    """Argument checks of the determinant-ratio calls run before any HIP call."""
+    L = q.lib()
+    for fn in (L.spline_eval_ratio_vgl, L.spline_eval_ratio_v):
+        assert fn(None, None, 4, None, 4, None, None, None) == -1
+        assert "handle" in q.last_error()

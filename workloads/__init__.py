@@ -18,15 +18,17 @@ the 80^3 grid with 384 orbitals mirrors the NiO-32 supercell of Table 1):
       U{64..1024} per table, electrons per walker = N of the table
   C5  the C2 table, with the surrogate's draws
 
-Seeds: ``SeedSequence(k)`` for workload k, spawned into six streams used in a
-fixed order: 0 coefficients/orbitals, 1 positions, 2 walker counts,
-3 surrogate initialisation, 4 surrogate training samples, 5 validation samples.
+Seeds: ``SeedSequence(k)`` for workload k, spawned into seven streams used in
+a fixed order: 0 coefficients/orbitals, 1 positions, 2 walker counts,
+3 surrogate initialisation, 4 surrogate training samples, 5 validation
+samples, 6 rows of inverse Slater matrices (determinant-ratio workloads).
 """
 from __future__ import annotations
 
 import numpy as np
 
-STREAM_COEFS, STREAM_POS, STREAM_WALKERS, STREAM_MLP_INIT, STREAM_MLP_TRAIN, STREAM_MLP_VAL = range(6)
+(STREAM_COEFS, STREAM_POS, STREAM_WALKERS, STREAM_MLP_INIT, STREAM_MLP_TRAIN, STREAM_MLP_VAL,
+ STREAM_AINV) = range(7)
 
 WORKLOADS = {
     1: dict(grid=(16, 16, 16), norb=32, walkers=1, electrons=1000, kind="uniform"),
@@ -38,9 +40,10 @@ RAGGED_TABLES = [((32, 32, 32), 64), ((48, 48, 48), 128), ((64, 64, 64), 256), (
 
 
 def rngs(k: int, seed: int | None = None) -> list[np.random.Generator]:
-    """Six independent generators for workload ``k`` (``seed`` overrides k)."""
+    """Seven independent generators for workload ``k`` (``seed`` overrides k).
+    Child i of the seed sequence does not depend on how many are spawned."""
     ss = np.random.SeedSequence(k if seed is None else seed)
-    return [np.random.default_rng(s) for s in ss.spawn(6)]
+    return [np.random.default_rng(s) for s in ss.spawn(7)]
 
 
 def gvectors(rmax: int = 4) -> np.ndarray:
@@ -166,3 +169,19 @@ def mlp_init(k: int = 5, seed: int | None = None, widths=(96, 256, 256, 192), nf
 def mlp_samples(k: int = 5, seed: int | None = None, count: int = 10**6, validation: bool = False):
     r = rngs(k, seed)[STREAM_MLP_VAL if validation else STREAM_MLP_TRAIN]
     return positions(r, count)
+
+
+def make_inverse_rows(k: int, count: int, norb: int, seed: int | None = None, dtype=np.float32) -> np.ndarray:
+    """[count][norb] stand-ins for rows of inverse Slater matrices: i.i.d.
+    N(0, 1/norb) entries (the size of the entries of the inverse of a
+    well-conditioned norb x norb matrix with O(1) entries).  Used where only
+    the shape and magnitude of the rows matter (throughput, sampled parity);
+    tests that need actual inverses build them from the oracle's matrices."""
+    r = rngs(k, seed)[STREAM_AINV]
+    out = np.empty((count, norb), dtype=dtype)
+    step = max(1, (1 << 24) // max(1, norb))
+    for i in range(0, count, step):
+        j = min(count, i + step)
+        out[i:j] = r.standard_normal((j - i, norb), dtype=np.float64 if dtype == np.float64 else np.float32)
+    out *= np.asarray(1.0 / np.sqrt(norb), dtype=dtype)
+    return out
