@@ -28,7 +28,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_UNIT = {"f32": 64 * 4 + 20, "bf16": 64 * 2 + 20, "f16": 64 * 2 + 20, "f64": 64 * 8 + 40}
 TUNE_CACHE = os.path.join(ROOT, "paper_1708_02645_amd", "tune_cache.txt")
-KERNEL_SOURCES = ["paper_1708_02645_amd/csrc/eval_kernel.hpp", "paper_1708_02645_amd/csrc/eval_f32.hip"]
+KERNEL_SOURCES = ["paper_1708_02645_amd/csrc/eval_kernel.hpp", "paper_1708_02645_amd/csrc/eval_f32.hip",
+                  "paper_1708_02645_amd/csrc/ratio_f32.hip", "paper_1708_02645_amd/csrc/shapes.hpp",
+                  "paper_1708_02645_amd/csrc/common.hpp"]
 
 
 def log(*a):
@@ -43,10 +45,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(tile) -> float | None:
+def traffic_from_profiles(tile, name: str = "vgl_f32_80cube_n384") -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source and tile shape."""
-    p = os.path.join(ROOT, "profiles", "vgl_f32_80cube_n384_traffic.json")
+    p = os.path.join(ROOT, "profiles", name + "_traffic.json")
     try:
         with open(p) as f:
             d = json.load(f)
@@ -287,7 +289,8 @@ def main() -> int:
              "f32_ratio_vgl": {"evals_per_s": units / (ms_rvgl * 1e-3), "ms_per_step": ms_rvgl,
                                "hbm_frac": units * bpu_rvgl / (ms_rvgl * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                "bytes_per_unit": bpu_rvgl, "speedup_vs_f32_vgl": ms32 / ms_rvgl,
-                               "eps": eps_ratio},
+                               "eps": eps_ratio,
+                               "traffic": traffic_from_profiles(tile32, "ratio_vgl_f32_80cube_n384")},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv,
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}
