@@ -50,6 +50,8 @@ def lib():
         L.oracle_eval_vgl.restype = ctypes.c_int
         L.oracle_eval_v.argtypes = [p, p, i32, p, i64, p, p, i32]
         L.oracle_eval_v.restype = ctypes.c_int
+        L.oracle_eval_vgh.argtypes = [p, p, i32, p, i64, p, p, p, p, i32]
+        L.oracle_eval_vgh.restype = ctypes.c_int
         L.oracle_round_sig.argtypes = [d, i32, i32]
         L.oracle_round_sig.restype = d
         L.oracle_dequantize.argtypes = [p, i64, i32, i32, p, p]
@@ -112,6 +114,26 @@ def eval_v(grid, coefs: np.ndarray, pos: np.ndarray, cell=(1.0, 1.0, 1.0), threa
     if rc != 0:
         raise ValueError("oracle_eval_v: bad arguments")
     return V
+
+
+def eval_vgh(grid, coefs: np.ndarray, pos: np.ndarray, lattice, threads: int = 0):
+    """V[B,N], G[B,3,N], H[B,6,N] (xx, xy, xz, yy, yz, zz) in FP64 for a
+    general cell: lattice[3,3] has the Cartesian lattice vectors as rows, and
+    grid axis d runs along lattice row d."""
+    coefs = np.ascontiguousarray(coefs, dtype=np.float64)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = np.ascontiguousarray(grid, dtype=np.int32)
+    lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+    N = coefs.shape[-1]
+    assert coefs.shape == tuple(int(x) for x in grid) + (N,)
+    B = pos.shape[0]
+    V = np.empty((B, N))
+    G = np.empty((B, 3, N))
+    H = np.empty((B, 6, N))
+    rc = lib().oracle_eval_vgh(_ptr(n), _ptr(lat), N, _ptr(coefs), B, _ptr(pos), _ptr(V), _ptr(G), _ptr(H), threads)
+    if rc != 0:
+        raise ValueError("oracle_eval_vgh: bad arguments or singular lattice")
+    return V, G, H
 
 
 def round_sig(x: float, p: int, emin: int) -> float:
