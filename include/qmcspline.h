@@ -166,6 +166,43 @@ int spline_eval_ratio_vgl(const spline_t* s, const double* pos_dev, int64_t B, c
 int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
                         int64_t ld, const int32_t* rows_dev, void* R, void* stream);
 
+/* General (triclinic) cells.
+ *
+ * spline_set_lattice gives the table a general cell.  lattice: host, 9
+ * doubles, row-major; row d is the Cartesian lattice vector a_d along which
+ * the n[d] grid points of axis d run (grid.cell is then ignored).  A position
+ * r = sum_d u_d a_d is reduced through its fractional coordinates
+ * u = r Lat^-1 in FP64, periodic with period 1 in each u_d.  Table 1's
+ * graphite cell is hexagonal, for example.  SPL_EINVAL if the matrix is not
+ * finite or is singular.  Host only; the table is not touched.  Afterwards
+ * spline_eval_vgh, spline_eval_vgl (a general-cell kernel that forms the
+ * Laplacian from the full Hessian), spline_eval_v, spline_eval_ratio_v and
+ * spline_autotune (which then tunes the general-cell kernels) serve the
+ * cell; spline_eval_ratio_vgl, plans and the surrogate's spline fallback
+ * return SPL_EUNSUPPORTED for such a table.
+ * spline_get_lattice returns it (diag(cell) for an orthorhombic table). */
+int spline_set_lattice(spline_t* s, const double* lattice);
+int spline_get_lattice(const spline_t* s, double* lattice);
+
+/* Value, gradient and full Hessian of all orbitals (the paper's Bspline-vgh
+ * kernel, Section 8; the Hessian is what a non-orthogonal cell needs for its
+ * Laplacian).  For any table, orthorhombic or general.
+ *   V device [B][n_orb], G device [B][3][n_orb] (Cartesian x, y, z),
+ *   H device [B][6][n_orb]: Cartesian xx, xy, xz, yy, yz, zz.
+ * Outputs float (double for SPL_F64); the ten grid-frame sums accumulate in
+ * FP32 (FP64) and are mapped to Cartesian axes with the inverse lattice.
+ * Conventions of spline_eval_vgl otherwise.  The VGH kernels have their own
+ * tile shapes: spline_vgh_tile_candidates / spline_set_vgh_tile /
+ * spline_get_vgh_tile, and spline_autotune_vgh times them all on a batch
+ * (outputs of every candidate must agree bit for bit, else SPL_EUNSUPPORTED). */
+int spline_eval_vgh(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* H,
+                    void* stream);
+int spline_vgh_tile_candidates(const spline_t* s, spline_tile* out, int32_t cap, int32_t* n);
+int spline_set_vgh_tile(spline_t* s, const spline_tile* tile);
+int spline_get_vgh_tile(const spline_t* s, spline_tile* tile);
+int spline_autotune_vgh(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* H,
+                        int32_t reps, void* stream, spline_tile* chosen);
+
 /* Tile shape control.  spline_tile_candidates lists the shapes valid for this
  * table (up to `cap`, count in *n); spline_set_tile validates and selects one. */
 int spline_tile_candidates(const spline_t* s, spline_tile* out, int32_t cap, int32_t* n);

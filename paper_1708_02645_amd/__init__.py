@@ -63,6 +63,13 @@ def lib():
             "spline_eval_vgl": ([p, p, i64, p, p, p, p], ctypes.c_int),
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
             "spline_eval_ratio_vgl": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
+            "spline_set_lattice": ([p, p], ctypes.c_int),
+            "spline_get_lattice": ([p, p], ctypes.c_int),
+            "spline_eval_vgh": ([p, p, i64, p, p, p, p], ctypes.c_int),
+            "spline_vgh_tile_candidates": ([p, p, i32, p], ctypes.c_int),
+            "spline_set_vgh_tile": ([p, p], ctypes.c_int),
+            "spline_get_vgh_tile": ([p, p], ctypes.c_int),
+            "spline_autotune_vgh": ([p, p, i64, p, p, p, i32, p, p], ctypes.c_int),
             "spline_eval_ratio_v": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
             "spline_tile_candidates": ([p, p, i32, p], ctypes.c_int),
             "spline_set_tile": ([p, p], ctypes.c_int),
@@ -229,6 +236,63 @@ class Spline:
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_v(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()), sp))
         return V
+
+    def set_lattice(self, lattice):
+        """Give the table a general cell: lattice[3,3] has the Cartesian
+        lattice vectors as rows; grid axis d runs along row d."""
+        lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+        check(lib().spline_set_lattice(self._h, lat.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_lattice(self) -> np.ndarray:
+        lat = np.empty(9)
+        check(lib().spline_get_lattice(self._h, lat.ctypes.data_as(ctypes.c_void_p)))
+        return lat.reshape(3, 3)
+
+    def alloc_vgh(self, B: int):
+        torch = self._torch
+        kw = dict(dtype=self.out_dtype, device=self.device)
+        return (torch.empty((B, self.norb), **kw), torch.empty((B, 3, self.norb), **kw),
+                torch.empty((B, 6, self.norb), **kw))
+
+    def eval_vgh(self, pos, out=None, stream=None):
+        """(V[B,N], G[B,3,N], H[B,6,N]) with H = Cartesian xx, xy, xz, yy, yz, zz."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V, G, H = out if out is not None else self.alloc_vgh(B)
+        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (H, (B, 6, self.norb))):
+            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("output tensor has wrong shape/dtype/device")
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_eval_vgh(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()),
+                                        ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(H.data_ptr()), sp))
+        return V, G, H
+
+    def vgh_tile_candidates(self):
+        n = ctypes.c_int32()
+        check(lib().spline_vgh_tile_candidates(self._h, None, 0, ctypes.byref(n)))
+        arr = (Tile * max(1, n.value))()
+        check(lib().spline_vgh_tile_candidates(self._h, arr, n.value, ctypes.byref(n)))
+        return [arr[i].astuple() for i in range(n.value)]
+
+    def set_vgh_tile(self, tile):
+        check(lib().spline_set_vgh_tile(self._h, ctypes.byref(Tile(*tile))))
+
+    def get_vgh_tile(self):
+        t = Tile()
+        check(lib().spline_get_vgh_tile(self._h, ctypes.byref(t)))
+        return t.astuple()
+
+    def autotune_vgh(self, pos, reps: int = 5, out=None, stream=None):
+        pos = self._pos(pos)
+        V, G, H = out if out is not None else self.alloc_vgh(pos.shape[0])
+        t = Tile()
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_autotune_vgh(self._h, ctypes.c_void_p(pos.data_ptr()), pos.shape[0],
+                                            ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                            ctypes.c_void_p(H.data_ptr()), reps, sp, ctypes.byref(t)))
+        return t.astuple()
 
     def _ratio(self, vgl, pos, ainv, ld, rows, out, stream):
         torch = self._torch

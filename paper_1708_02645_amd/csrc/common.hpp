@@ -51,6 +51,12 @@ struct EvalArgs {
     const void* ainv;
     int64_t ald;
     const int32_t* arows;
+    // General (triclinic) cell: when `general` is set, a position r is reduced
+    // through its fractional coordinates u_d = sum_c r_c ilat[c*3+d] (ilat =
+    // inverse of the lattice matrix whose rows are the lattice vectors) and the
+    // derivative weights are in grid units (d/dt_d).
+    double ilat[9];
+    int32_t general;
 };
 
 // One task of a multi-table plan: positions [first, first + count) of table
@@ -110,6 +116,12 @@ const Variant* find_variant(spline_dtype st, int cw, int nch, int lpp, bool vgl,
 int64_t tiles_of(const spline_s* s, const spline_tile& t);
 EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G,
                    void* L);
+// General cells and the VGH family (vgh_host.cpp).
+spline_tile default_vgh_tile(const spline_s* s);
+void set_general_args(const spline_s* s, EvalArgs& a);
+int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
+int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, void* G, void* H, int32_t reps,
+                 hipStream_t st, spline_tile* chosen);
 
 }  // namespace qs
 
@@ -123,4 +135,8 @@ struct spline_s {
     int device;            // HIP device id the table lives on
     spline_tile tile;      // current VGL tile shape
     spline_tile vtile;     // current value-only tile shape
+    spline_tile htile;     // current shape of the VGH family (also general-cell VGL)
+    int general;           // 1 once a general lattice is set
+    double lat[9];         // lattice vectors as rows (general cells)
+    double ilat[9];        // its inverse
 };

@@ -72,7 +72,8 @@ __device__ inline void axis_weights(T t, T g, T g2, T* w)
 }
 
 // FP64 lattice reduction of one coordinate: periodic wrap, lower cell,
-// clamp to [0, n-1]; non-finite input gives cell 0 and t = NaN.
+// clamp to [0, n-1]; non-finite input gives cell 0 and t = NaN.  In a general
+// cell the coordinate is the fractional one and cell = 1.
 __device__ inline void lattice_reduce(double r, double cell, int n, int& i, double& t)
 {
     if (!__builtin_isfinite(r)) {
@@ -98,12 +99,22 @@ __device__ inline void stage_position(const EvalArgs& a, int64_t b, PosW<TA>& w)
     const int64_t row = a.idx ? (int64_t)a.idx[b] : b;
 #pragma unroll
     for (int d = 0; d < 3; ++d) r[d] = a.pos[3 * row + d];  // all three loads in flight together
+    if (a.general) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double t;
-        lattice_reduce(r[d], a.cell[d], a.n[d], i[d], t);
-        const double g = (double)a.n[d] / a.cell[d];
-        axis_weights<TA>((TA)t, (TA)g, (TA)(g * g), w.w[d]);
+        for (int d = 0; d < 3; ++d) {
+            const double u = r[0] * a.ilat[d] + r[1] * a.ilat[3 + d] + r[2] * a.ilat[6 + d];
+            double t;
+            lattice_reduce(u, 1.0, a.n[d], i[d], t);
+            axis_weights<TA>((TA)t, TA(1), TA(1), w.w[d]);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double t;
+            lattice_reduce(r[d], a.cell[d], a.n[d], i[d], t);
+            const double g = (double)a.n[d] / a.cell[d];
+            axis_weights<TA>((TA)t, (TA)g, (TA)(g * g), w.w[d]);
+        }
     }
     w.off = (int64_t)i[0] * a.xstride + (int64_t)i[1] * a.ystride + (int64_t)i[2] * a.row_bytes;
     w.row = row;

@@ -583,6 +583,7 @@ int spline_mlp_eval_vgl(const spline_mlp_t* m, const spline_t* fallback, float t
     if (rc || !fallback) return rc;
     if (fallback->norb != m->nout || fallback->store == SPL_F64)
         return fail(SPL_EINVAL, "fallback table must have N orbitals and FP32 outputs");
+    if (fallback->general) return fail(SPL_EUNSUPPORTED, "the fallback table must have an orthorhombic cell");
     for (int d = 0; d < 3; ++d)
         if (fallback->grid.cell[d] != m->cell[d]) return fail(SPL_EINVAL, "fallback table and network cells differ");
     if (!ws || ws_bytes < spline_mlp_eval_workspace_bytes(B)) return fail(SPL_ENOMEM, "workspace too small");

@@ -186,6 +186,7 @@ int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     for (int32_t t = 0; t < n_tabs; ++t) {
         if (!tabs[t]) return fail(SPL_EINVAL, "NULL table handle");
         if (tabs[t]->store != tabs[0]->store) return fail(SPL_EUNSUPPORTED, "tables of one plan must share the storage type");
+        if (tabs[t]->general) return fail(SPL_EUNSUPPORTED, "plans are built for orthorhombic cells only");
         if (tabs[t]->device != dev) return fail(SPL_EINVAL, "table lives on another device");
         if (B_per_tab[t] > 0 && (!pos_dev[t] || !V[t] || !G[t] || !L[t]))
             return fail(SPL_EINVAL, "NULL position or output pointer");

@@ -359,6 +359,7 @@ EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, i
     a.norb = s->norb;
     a.tiles = (int32_t)tiles_of(s, t);
     a.pb = t.pb;
+    if (s->general) set_general_args(s, a);
     return a;
 }
 
@@ -412,7 +413,9 @@ int spline_create(const spline_grid* grid, int32_t n_orb, const double* coefs_ho
     s->device = dev;
     s->tile = default_tile(s, true);
     s->vtile = default_tile(s, false);
-    if (s->tile.cw == 0 || s->vtile.cw == 0) {
+    s->htile = default_vgh_tile(s);
+    s->general = 0;
+    if (s->tile.cw == 0 || s->vtile.cw == 0 || s->htile.cw == 0) {
         delete s;
         return fail(SPL_EUNSUPPORTED, "no compiled tile shape fits this row width");
     }
@@ -445,6 +448,7 @@ static int eval_common(const spline_t* s, const double* pos, int64_t B, void* V,
     if (!pos || !V || (vgl && (!G || !L))) return fail(SPL_EINVAL, "NULL position or output pointer");
     int64_t tmp;
     if (!mul_ok(B, (int64_t)s->norb * 3 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    if (s->general && vgl) return vgl_general(s, pos, B, V, G, L, static_cast<hipStream_t>(stream));
     return run_eval(s, vgl ? s->tile : s->vtile, vgl, pos, B, V, G, L, static_cast<hipStream_t>(stream));
 }
 
@@ -474,6 +478,8 @@ static int ratio_common(const spline_t* s, const double* pos, int64_t B, const v
         return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
     int64_t tmp;
     if (!mul_ok(B, 5 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    if (s->general && vgl)
+        return fail(SPL_EUNSUPPORTED, "ratio with derivatives is built for orthorhombic cells only");
     spline_tile t = vgl ? s->tile : s->vtile;
     const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
     if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");
@@ -594,6 +600,7 @@ extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, vo
     if (B <= 0 || !pos_dev || !V || !G || !L) return fail(SPL_EINVAL, "autotune needs a non-empty batch and outputs");
     if (reps < 1) reps = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->general) return vgh_autotune(s, 1 /* general-cell VGL */, pos_dev, B, V, G, L, reps, st, chosen);
     const std::string key = tune_key(s, B);
     if (cache_path) {
         spline_tile t{};
