@@ -304,6 +304,45 @@ def main() -> int:
             del s, out
             torch.cuda.empty_cache()
 
+    # Value-gradient-Hessian (the paper's Bspline-vgh) on the same table and
+    # batch: orthorhombic cell, and a hexagonal cell (graphite-like lattice
+    # a1 = (1,0,0), a2 = (-1/2, sqrt(3)/2, 0), a3 = (0,0,1.6); positions are
+    # the same fractional coordinates mapped into it), with the general-cell
+    # VGL beside it.
+    log("bench: VGH forms ...")
+    hexl = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3.0) / 2.0, 0.0], [0.0, 0.0, 1.6]])
+    pos_hex = torch.from_numpy(pos_np @ hexl).to(dev)
+    sh = q.Spline(grid, coefs, "f32", device=dev)
+    vgh_out = sh.alloc_vgh(B)
+    t_vgh = sh.autotune_vgh(pos, reps=2, out=vgh_out)
+    ms_vgh, _ = time_steps(torch, lambda: sh.eval_vgh(pos, out=vgh_out), args.steps, args.warmup)
+    sh.set_lattice(hexl)
+    t_vgh_hex = sh.autotune_vgh(pos_hex, reps=2, out=vgh_out)
+    ms_vgh_hex, _ = time_steps(torch, lambda: sh.eval_vgh(pos_hex, out=vgh_out), args.steps, args.warmup)
+    Vh, Gh, Hh = vgh_out
+    Lbuf = torch.empty((B, N), dtype=torch.float32, device=dev)
+    ms_vgl_hex, _ = time_steps(torch, lambda: sh.eval_vgl(pos_hex, out=(Vh, Gh, Lbuf)), args.steps, args.warmup)
+    hidx = idx[:128]
+    hit = torch.from_numpy(hidx).to(dev)
+    sh.eval_vgh(pos_hex, out=vgh_out)
+    ref_h = oracle.eval_vgh(grid, coefs, pos_np[hidx] @ hexl, hexl)
+    eps_h = [oracle.rel_err(t[hit].double().cpu().numpy(), r) for t, r in zip(vgh_out, ref_h)]
+    del sh, vgh_out, Vh, Gh, Hh, Lbuf, pos_hex
+    torch.cuda.empty_cache()
+    bpu_vgh = 64 * 4 + 40
+    forms["f32_vgh"] = {"evals_per_s": units / (ms_vgh * 1e-3), "ms_per_step": ms_vgh, "tile": list(t_vgh),
+                        "bytes_per_unit": bpu_vgh,
+                        "hbm_frac": units * bpu_vgh / (ms_vgh * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    forms["f32_vgh_hexagonal"] = {
+        "evals_per_s": units / (ms_vgh_hex * 1e-3), "ms_per_step": ms_vgh_hex, "tile": list(t_vgh_hex),
+        "bytes_per_unit": bpu_vgh, "hbm_frac": units * bpu_vgh / (ms_vgh_hex * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "eps_V": eps_h[0], "eps_G": eps_h[1], "eps_H": eps_h[2]}
+    forms["f32_vgl_hexagonal"] = {
+        "evals_per_s": units / (ms_vgl_hex * 1e-3), "ms_per_step": ms_vgl_hex, "tile": list(t_vgh_hex),
+        "bytes_per_unit": BYTES_PER_UNIT["f32"],
+        "hbm_frac": units * BYTES_PER_UNIT["f32"] / (ms_vgl_hex * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    log("bench: vgh %.3f ms, vgh hexagonal %.3f ms, vgl hexagonal %.3f ms" % (ms_vgh, ms_vgh_hex, ms_vgl_hex))
+
     if not args.no_ragged:
         # Ragged workload: four tables (32^3/48^3/64^3/80^3, N = 64/128/256/384,
         # FP32) with U{64..1024} walkers each, in one graph-captured
