@@ -160,6 +160,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
+    ap.add_argument("--vgh-tile", type=str, default="", help="cw,nch,lpp,pb for the VGH forms (skips their autotuner)")
     ap.add_argument("--no-tune-cache", dest="use_tune_cache", action="store_false",
                     help="search tile shapes afresh instead of reading the committed tuning cache")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -241,6 +242,7 @@ def main() -> int:
     e32 = eps(out32)
     # value only (the quadrature-point evaluation): same table and positions
     ms_v, _ = time_steps(torch, lambda: s32.eval_v(pos, out=out32[0]), args.steps, args.warmup)
+    vtile32 = s32.get_value_tile()
     del out32
     torch.cuda.empty_cache()
 
@@ -283,7 +285,7 @@ def main() -> int:
 
     forms = {"f32": {"evals_per_s": evals, "ms_per_step": ms32, "tile": list(tile32),
                      "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]},
-             "f32_value_only": {"evals_per_s": units / (ms_v * 1e-3), "ms_per_step": ms_v,
+             "f32_value_only": {"evals_per_s": units / (ms_v * 1e-3), "ms_per_step": ms_v, "tile": list(vtile32),
                                 "hbm_frac": units * (64 * 4 + 4) / (ms_v * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                 "bytes_per_unit": 64 * 4 + 4},
              "f32_ratio_vgl": {"evals_per_s": units / (ms_rvgl * 1e-3), "ms_per_step": ms_rvgl,
@@ -291,7 +293,7 @@ def main() -> int:
                                "bytes_per_unit": bpu_rvgl, "speedup_vs_f32_vgl": ms32 / ms_rvgl,
                                "eps": eps_ratio,
                                "traffic": traffic_from_profiles(tile32, "ratio_vgl_f32_80cube_n384")},
-             "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv,
+             "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}
     if not args.no_forms:
@@ -314,10 +316,18 @@ def main() -> int:
     pos_hex = torch.from_numpy(pos_np @ hexl).to(dev)
     sh = q.Spline(grid, coefs, "f32", device=dev)
     vgh_out = sh.alloc_vgh(B)
-    t_vgh = sh.autotune_vgh(pos, reps=2, out=vgh_out)
+    vgh_tile = tuple(int(x) for x in args.vgh_tile.split(",")) if args.vgh_tile else None
+
+    def pick_vgh(p):
+        if vgh_tile:
+            sh.set_vgh_tile(vgh_tile)
+            return vgh_tile
+        return sh.autotune_vgh(p, reps=2, out=vgh_out)
+
+    t_vgh = pick_vgh(pos)
     ms_vgh, _ = time_steps(torch, lambda: sh.eval_vgh(pos, out=vgh_out), args.steps, args.warmup)
     sh.set_lattice(hexl)
-    t_vgh_hex = sh.autotune_vgh(pos_hex, reps=2, out=vgh_out)
+    t_vgh_hex = pick_vgh(pos_hex)
     ms_vgh_hex, _ = time_steps(torch, lambda: sh.eval_vgh(pos_hex, out=vgh_out), args.steps, args.warmup)
     Vh, Gh, Hh = vgh_out
     Lbuf = torch.empty((B, N), dtype=torch.float32, device=dev)

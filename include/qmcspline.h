@@ -212,12 +212,17 @@ int spline_get_tile(const spline_t* s, spline_tile* tile);
 /* Autotuner: times every candidate tile shape on the given batch with HIP
  * events (`reps` timed launches each, after one warm-up), checks that every
  * candidate's outputs on the first positions are bit-identical to the first
- * candidate's, selects the fastest and writes it to *chosen.  With a
- * non-NULL cache_path, a matching entry (key: device arch, grid, n_orb,
- * store, B bucket) is used without searching, and a new result is appended;
- * an unreadable or corrupt cache is ignored.  Outputs V/G/L are overwritten. */
+ * candidate's, and selects the fastest, separately for VGL (written to
+ * *chosen) and for value-only evaluation (read back with
+ * spline_get_value_tile; the value-only and value-ratio kernels use it).
+ * With a non-NULL cache_path, matching entries (key: device arch, grid,
+ * n_orb, store, B bucket; " V" appended for value only) are used without
+ * searching, and new results are appended; an unreadable or corrupt cache is
+ * ignored.  Outputs V/G/L are overwritten.  For a table with a general
+ * lattice it tunes the general-cell VGL kernels instead (no cache). */
 int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
                     int32_t reps, const char* cache_path, void* stream, spline_tile* chosen);
+int spline_get_value_tile(const spline_t* s, spline_tile* tile);
 
 /* ---- Ragged multi-table plans --------------------------------------------
  * The walker population fluctuates from generation to generation and each

@@ -74,6 +74,7 @@ def lib():
             "spline_tile_candidates": ([p, p, i32, p], ctypes.c_int),
             "spline_set_tile": ([p, p], ctypes.c_int),
             "spline_get_tile": ([p, p], ctypes.c_int),
+            "spline_get_value_tile": ([p, p], ctypes.c_int),
             "spline_autotune": ([p, p, i64, p, p, p, i32, ctypes.c_char_p, p, p], ctypes.c_int),
             "spline_get_info": ([p, p, p, p, p], ctypes.c_int),
             "spline_destroy": ([p], ctypes.c_int),
@@ -267,6 +268,11 @@ class Spline:
             check(lib().spline_eval_vgh(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()),
                                         ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(H.data_ptr()), sp))
         return V, G, H
+
+    def get_value_tile(self):
+        t = Tile()
+        check(lib().spline_get_value_tile(self._h, ctypes.byref(t)))
+        return t.astuple()
 
     def vgh_tile_candidates(self):
         n = ctypes.c_int32()

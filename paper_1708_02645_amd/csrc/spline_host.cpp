@@ -547,6 +547,13 @@ int spline_get_tile(const spline_t* s, spline_tile* tile)
     return SPL_OK;
 }
 
+int spline_get_value_tile(const spline_t* s, spline_tile* tile)
+{
+    if (!s || !tile) return fail(SPL_EINVAL, "NULL argument");
+    *tile = s->vtile;
+    return SPL_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -593,52 +600,40 @@ static bool cache_lookup(const char* path, const std::string& key, spline_tile* 
 
 }  // namespace qs
 
-extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L, int32_t reps,
-                               const char* cache_path, void* stream, spline_tile* chosen)
-{
-    if (!s) return fail(SPL_EINVAL, "handle is NULL");
-    if (B <= 0 || !pos_dev || !V || !G || !L) return fail(SPL_EINVAL, "autotune needs a non-empty batch and outputs");
-    if (reps < 1) reps = 1;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (s->general) return vgh_autotune(s, 1 /* general-cell VGL */, pos_dev, B, V, G, L, reps, st, chosen);
-    const std::string key = tune_key(s, B);
-    if (cache_path) {
-        spline_tile t{};
-        if (cache_lookup(cache_path, key, &t) && check_tile(s, &t, true) == SPL_OK) {
-            s->tile = t;
-            if (find_variant(s->store, t.cw, t.nch, t.lpp, false)) s->vtile = t;
-            if (chosen) *chosen = t;
-            return SPL_OK;
-        }
-    }
-    int32_t n = 0;
-    int rc = spline_tile_candidates(s, nullptr, 0, &n);
-    if (rc) return rc;
-    std::vector<spline_tile> cands(n);
-    spline_tile_candidates(s, cands.data(), n, &n);
-    if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
+namespace qs {
 
+// Times every candidate shape for VGL (vgl) or value-only evaluation and
+// returns the fastest in *best.  Every candidate must reproduce the first
+// one's outputs bit for bit (the accumulation order does not depend on the
+// tile shape).
+static int tune_kind(spline_s* s, bool vgl, const std::vector<spline_tile>& cands, const double* pos, int64_t B,
+                     void* V, void* G, void* L, int32_t reps, hipStream_t st, spline_tile* best_t)
+{
     const int64_t Bc = std::min<int64_t>(B, 512);
     const size_t ob = s->store == SPL_F64 ? 8 : 4;
     const size_t nv = (size_t)Bc * s->norb * ob;
-    std::vector<unsigned char> ref(nv * 5), cur(nv * 5);
+    const size_t nq = vgl ? 5 : 1;
+    std::vector<unsigned char> ref, cur(nv * nq);
     hipEvent_t e0, e1;
     QS_HIP(hipEventCreate(&e0));
     QS_HIP(hipEventCreate(&e1));
+    int rc = SPL_OK;
     float best = 1e30f;
-    spline_tile best_t = cands[0];
-    for (int32_t i = 0; i < n; ++i) {
-        const spline_tile& t = cands[i];
-        rc = run_eval(s, t, true, pos_dev, B, V, G, L, st);
+    *best_t = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        spline_tile t = cands[i];
+        if (!vgl && !find_variant(s->store, t.cw, t.nch, t.lpp, false)) continue;
+        rc = run_eval(s, t, vgl, pos, B, V, G, L, st);
         if (rc) break;
-        if (hipMemcpyAsync(cur.data(), V, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(cur.data() + nv, G, 3 * nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(cur.data() + 4 * nv, L, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
+        bool copied = hipMemcpyAsync(cur.data(), V, nv, hipMemcpyDeviceToHost, st) == hipSuccess;
+        if (vgl)
+            copied = copied && hipMemcpyAsync(cur.data() + nv, G, 3 * nv, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                     hipMemcpyAsync(cur.data() + 4 * nv, L, nv, hipMemcpyDeviceToHost, st) == hipSuccess;
+        if (!copied || hipStreamSynchronize(st) != hipSuccess) {
             rc = fail(SPL_EHIP, "autotune: copy of outputs failed");
             break;
         }
-        if (i == 0) {
+        if (ref.empty()) {
             ref = cur;
         } else if (std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
             std::ostringstream m;
@@ -648,7 +643,7 @@ extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, vo
             break;
         }
         if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SPL_EHIP, "event record"); break; }
-        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = run_eval(s, t, true, pos_dev, B, V, G, L, st);
+        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = run_eval(s, t, vgl, pos, B, V, G, L, st);
         if (rc) break;
         float ms = 0.f;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -658,18 +653,57 @@ extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, vo
         }
         if (ms < best) {
             best = ms;
-            best_t = t;
+            *best_t = t;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace qs
+
+// The VGL and the value-only shapes are tuned separately; cache lines are
+// "<key>|cw nch lpp pb" for VGL and "<key> V|cw nch lpp pb" for value only.
+extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L, int32_t reps,
+                               const char* cache_path, void* stream, spline_tile* chosen)
+{
+    if (!s) return fail(SPL_EINVAL, "handle is NULL");
+    if (B <= 0 || !pos_dev || !V || !G || !L) return fail(SPL_EINVAL, "autotune needs a non-empty batch and outputs");
+    if (reps < 1) reps = 1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->general) return vgh_autotune(s, 1 /* general-cell VGL */, pos_dev, B, V, G, L, reps, st, chosen);
+    const std::string key = tune_key(s, B), vkey = key + " V";
+    spline_tile tv{}, tn{};
+    const bool have_v = cache_path && cache_lookup(cache_path, key, &tv) && check_tile(s, &tv, true) == SPL_OK;
+    const bool have_n = cache_path && cache_lookup(cache_path, vkey, &tn) && check_tile(s, &tn, false) == SPL_OK;
+    if (have_v && have_n) {
+        s->tile = tv;
+        s->vtile = tn;
+        if (chosen) *chosen = tv;
+        return SPL_OK;
+    }
+    int32_t n = 0;
+    int rc = spline_tile_candidates(s, nullptr, 0, &n);
     if (rc) return rc;
-    s->tile = best_t;
-    if (find_variant(s->store, best_t.cw, best_t.nch, best_t.lpp, false)) s->vtile = best_t;
-    if (chosen) *chosen = best_t;
+    std::vector<spline_tile> cands(n);
+    spline_tile_candidates(s, cands.data(), n, &n);
+    if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
+    if (!have_v) {
+        rc = tune_kind(s, true, cands, pos_dev, B, V, G, L, reps, st, &tv);
+        if (rc) return rc;
+    }
+    if (!have_n) {
+        rc = tune_kind(s, false, cands, pos_dev, B, V, G, L, reps, st, &tn);
+        if (rc) return rc;
+    }
+    s->tile = tv;
+    s->vtile = tn;
+    if (chosen) *chosen = tv;
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        if (f) f << key << "|" << best_t.cw << " " << best_t.nch << " " << best_t.lpp << " " << best_t.pb << "\n";
+        if (f && !have_v) f << key << "|" << tv.cw << " " << tv.nch << " " << tv.lpp << " " << tv.pb << "\n";
+        if (f && !have_n) f << vkey << "|" << tn.cw << " " << tn.nch << " " << tn.lpp << " " << tn.pb << "\n";
     }
     return SPL_OK;
 }
