@@ -37,9 +37,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+VGH_SOURCES = KERNEL_SOURCES + ["paper_1708_02645_amd/csrc/vgh_kernel.hpp", "paper_1708_02645_amd/csrc/vgh_f32.hip"]
+
+
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -54,7 +57,8 @@ def traffic_from_profiles(tile, name: str = "vgl_f32_80cube_n384") -> float | No
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_hash() or tuple(d.get("tile", ())) != tuple(tile):
+    srcs = VGH_SOURCES if name.startswith("vgh") else KERNEL_SOURCES
+    if d.get("kernel_hash") != kernel_hash(srcs) or tuple(d.get("tile", ())) != tuple(tile):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -346,7 +350,8 @@ def main() -> int:
     forms["f32_vgh_hexagonal"] = {
         "evals_per_s": units / (ms_vgh_hex * 1e-3), "ms_per_step": ms_vgh_hex, "tile": list(t_vgh_hex),
         "bytes_per_unit": bpu_vgh, "hbm_frac": units * bpu_vgh / (ms_vgh_hex * 1e-3) / 1e9 / PEAK_HBM_GBS,
-        "eps_V": eps_h[0], "eps_G": eps_h[1], "eps_H": eps_h[2]}
+        "eps_V": eps_h[0], "eps_G": eps_h[1], "eps_H": eps_h[2],
+        "traffic": traffic_from_profiles(t_vgh_hex, "vgh_f32_80cube_n384")}
     forms["f32_vgl_hexagonal"] = {
         "evals_per_s": units / (ms_vgl_hex * 1e-3), "ms_per_step": ms_vgl_hex, "tile": list(t_vgh_hex),
         "bytes_per_unit": BYTES_PER_UNIT["f32"],
