@@ -200,6 +200,19 @@ template <typename TA, int VPC>
 __device__ inline void store_vals(TA* dst, const TA* v, int o, int norb, bool aligned)
 {
     if (aligned && o + VPC <= norb) {
+        if constexpr (VPC == 2 || VPC == 4) {
+            // outputs are written once and not read back here: non-temporal
+            typedef TA vec __attribute__((ext_vector_type(VPC)));
+            vec x;
+#pragma unroll
+            for (int i = 0; i < VPC; ++i) x[i] = v[i];
+            __builtin_nontemporal_store(x, reinterpret_cast<vec*>(dst + o));
+            return;
+        }
+        if constexpr (VPC == 1) {
+            __builtin_nontemporal_store(v[0], dst + o);
+            return;
+        }
         Pack<TA, VPC> p;
 #pragma unroll
         for (int i = 0; i < VPC; ++i) p.v[i] = v[i];
