@@ -11,11 +11,15 @@ The gradient and the Laplacian of det A' with respect to r'_k, divided by
 det A, are the same dot product with the orbital gradients and Laplacians
 (the "derivatives" step of Algorithm 1), because det A' is linear in column k.
 
+When the move is accepted, A^-1 is updated with the Sherman-Morrison
+formula (``sherman_morrison``).
+
 Everything here is the plain definition: the orbital V, G, L from the FP64
-spline oracle, then one dot product per position with the given row.  Pinned
-in ``tests/test_oracle_det.py`` against determinants computed directly with
-``numpy.linalg`` (ratio) and against central differences of those
-determinants (gradient, Laplacian).
+spline oracle, then one dot product per position with the given row; the
+update is the rank-one formula written out.  Pinned in
+``tests/test_oracle_det.py`` against determinants and inverses computed
+directly with ``numpy.linalg`` (ratio, update) and against central
+differences of those determinants (gradient, Laplacian).
 """
 from __future__ import annotations
 
@@ -59,3 +63,15 @@ def ratio_scale(rows: np.ndarray, Qref_max: np.ndarray) -> np.ndarray:
     measured (an error of e * M_i in every orbital moves the dot product by at
     most e times this)."""
     return np.abs(np.asarray(rows, dtype=np.float64)) @ np.asarray(Qref_max, dtype=np.float64)
+
+
+def sherman_morrison(ainv: np.ndarray, k: int, phi: np.ndarray) -> np.ndarray:
+    """Inverse after the move of electron k is accepted (Section 3: A^-1 is
+    updated with the Sherman-Morrison formula).  Column k of A becomes phi =
+    (phi_1(r'_k), ..., phi_n(r'_k)); with t = A^-1 phi and rho = t_k (the
+    determinant ratio), the new inverse is A^-1 - (t - e_k) (row k of A^-1) / rho."""
+    a = np.asarray(ainv, dtype=np.float64)
+    t = a @ np.asarray(phi, dtype=np.float64)
+    u = t.copy()
+    u[k] -= 1.0
+    return a - np.outer(u, a[k]) / t[k]

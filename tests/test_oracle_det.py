@@ -103,3 +103,33 @@ def test_ratio_scale_bounds_perturbation(oracle):
     for _ in range(20):
         err = rng.uniform(-1, 1, size=(7, 11)) * M * 1e-3
         assert np.all(np.abs(np.sum(rows * err, axis=1)) <= 1e-3 * s * (1 + 1e-12))
+
+
+def test_sherman_morrison_is_the_inverse_of_the_moved_matrix(oracle):
+    """The updated inverse equals numpy's inverse of the Slater matrix rebuilt
+    with the moved electron; a sweep of accepted moves over every electron
+    equals the inverse of the final matrix."""
+    from oracle import det
+
+    grid, n, coefs, R, Rp = _system((1.0, 1.0, 1.0), 23)
+    A = det.slater_matrix(grid, coefs, R)
+    Ainv = np.linalg.inv(A)
+    R2 = R.copy()
+    for k in range(n):
+        phi = oracle.eval_v(grid, coefs, Rp[k:k + 1])[0]
+        new = det.sherman_morrison(Ainv, k, phi)
+        R2[k] = Rp[k]
+        want = np.linalg.inv(det.slater_matrix(grid, coefs, R2))
+        assert np.max(np.abs(new - want)) < 1e-8 * np.max(np.abs(want)), k
+        Ainv = new
+    # a wrong sign of the correction or the column in place of the row fails
+    a0 = np.linalg.inv(A)
+    phi = oracle.eval_v(grid, coefs, Rp[:1])[0]
+    R3 = R.copy()
+    R3[0] = Rp[0]
+    want = np.linalg.inv(det.slater_matrix(grid, coefs, R3))
+    t = a0 @ phi
+    u = t.copy()
+    u[0] -= 1.0
+    wrong = a0 + np.outer(u, a0[0]) / t[0]
+    assert np.max(np.abs(wrong - want)) > 1e-3 * np.max(np.abs(want))
