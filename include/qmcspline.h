@@ -166,6 +166,29 @@ int spline_eval_ratio_vgl(const spline_t* s, const double* pos_dev, int64_t B, c
 int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
                         int64_t ld, const int32_t* rows_dev, void* R, void* stream);
 
+/* Sherman-Morrison update of inverse Slater matrices after accepted moves
+ * (Section 3: once the proposed r'_k is accepted, A^-1 is updated with the
+ * Sherman-Morrison formula).  For each slot j in [0, count): walker
+ * w = walkers_dev ? walkers_dev[j] : j, electron k = k_dev[j], and
+ * phi = phi_dev + j*ld_phi, the n orbital values at the accepted position
+ * (spline_eval_v gives them).  The n x n row-major inverse of walker w, at
+ * ainv_dev + w*walker_stride elements, becomes the inverse of A with column k
+ * replaced by phi:  t = A^-1 phi,  rho = t_k (the determinant ratio),
+ * A^-1 <- A^-1 - (t - e_k)(row k of A^-1)/rho.  In place; every row is read
+ * and written once (two launches: rows i != k, then row k).
+ *   dtype       SPL_F32 or SPL_F64: element type of ainv and phi (the
+ *               paper's mixed-precision code keeps A^-1 in single precision)
+ *   n           orbitals = electrons of the determinant, with (2n+4) elements
+ *               fitting in 64 KB of LDS (n <= 8190 FP32, 4094 FP64)
+ *   walker_stride >= n*n; ld_phi >= n; pointers element-aligned
+ * A slot with k outside [0, n) or a negative walker index leaves its walker
+ * untouched.  Listing one walker twice in a call races; rho == 0 (a move that
+ * must not be accepted) gives non-finite entries.  Asynchronous on `stream`;
+ * count == 0 is a no-op.  SPL_EINVAL on bad sizes or pointers. */
+int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const int32_t* walkers_dev,
+                      const int32_t* k_dev, const void* phi_dev, int64_t ld_phi, int64_t count,
+                      spline_dtype dtype, void* stream);
+
 /* General (triclinic) cells.
  *
  * spline_set_lattice gives the table a general cell.  lattice: host, 9

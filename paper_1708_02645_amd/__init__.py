@@ -63,6 +63,7 @@ def lib():
             "spline_eval_vgl": ([p, p, i64, p, p, p, p], ctypes.c_int),
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
             "spline_eval_ratio_vgl": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
+            "spline_det_update": ([p, i32, i64, p, p, p, i64, i64, ctypes.c_int, p], ctypes.c_int),
             "spline_set_lattice": ([p, p], ctypes.c_int),
             "spline_get_lattice": ([p, p], ctypes.c_int),
             "spline_eval_vgh": ([p, p, i64, p, p, p, p], ctypes.c_int),
@@ -148,6 +149,38 @@ def probe_stream_read(buf, grid: int = 1024, out=None, stream=None):
     check(lib().spline_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
                                          ctypes.c_void_p(out.data_ptr()), int(grid), sp))
     return out
+
+
+def det_update(ainv, k, phi, walkers=None, stream=None):
+    """Sherman-Morrison update, in place, of the inverses ainv[W, n, n] (float32
+    or float64, contiguous, on a GPU) after accepted moves: slot j updates
+    walker walkers[j] (or j) for electron k[j] with orbital values phi[j, :n]."""
+    import torch
+
+    if not (isinstance(ainv, torch.Tensor) and ainv.is_cuda and ainv.dim() == 3 and ainv.shape[1] == ainv.shape[2]
+            and ainv.is_contiguous() and ainv.dtype in (torch.float32, torch.float64)):
+        raise ValueError("ainv must be a contiguous [W, n, n] float32/float64 GPU tensor")
+    W_, n = ainv.shape[0], ainv.shape[1]
+    count = k.shape[0]
+    for t, what in ((k, "k"),) + (((walkers, "walkers"),) if walkers is not None else ()):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.int32 and t.device == ainv.device
+                and t.is_contiguous() and tuple(t.shape) == (count,)):
+            raise ValueError("%s must be a contiguous int32 [count] tensor on the same device" % what)
+    if not (isinstance(phi, torch.Tensor) and phi.dtype == ainv.dtype and phi.device == ainv.device
+            and phi.dim() == 2 and phi.shape[0] == count and phi.shape[1] >= n and phi.stride(1) == 1):
+        raise ValueError("phi must be a [count, >=n] tensor of the inverse's dtype with unit column stride")
+    if walkers is None and count > W_:
+        raise ValueError("more slots than walkers")
+    if walkers is not None and count and (int(walkers.min().item()) < 0 or int(walkers.max().item()) >= W_):
+        raise ValueError("walker index out of range")
+    dt = DTYPES["f64" if ainv.dtype == torch.float64 else "f32"]
+    with torch.cuda.device(ainv.device):
+        sp, _ = _stream_ptr(torch, ainv.device, stream)
+        check(lib().spline_det_update(ctypes.c_void_p(ainv.data_ptr()), n, n * n,
+                                      ctypes.c_void_p(walkers.data_ptr()) if walkers is not None else None,
+                                      ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(phi.data_ptr()), phi.stride(0),
+                                      count, dt, sp))
+    return ainv
 
 
 def _stream_ptr(torch, device, stream):

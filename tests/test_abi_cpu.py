@@ -148,3 +148,10 @@ def test_ratio_entry_points_reject_bad_arguments_without_a_gpu():
     for fn in (L.spline_eval_ratio_vgl, L.spline_eval_ratio_v):
         assert fn(None, None, 4, None, 4, None, None, None) == -1
         assert "handle" in q.last_error()
+
+
+def test_det_update_rejects_bad_arguments_without_a_gpu():
+    L = q.lib()
+    assert L.spline_det_update(None, 4, 16, None, None, None, 4, 0, 1, None) == 0  # empty: no-op
+    assert L.spline_det_update(None, 4, 16, None, None, None, 4, 1, 1, None) == -1
+    assert L.spline_det_update(None, 4, 16, None, None, None, 4, -1, 1, None) == -1
