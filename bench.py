@@ -271,7 +271,16 @@ def main() -> int:
     rit = torch.from_numpy(ridx).to(dev)
     eps_ratio = float(np.max(np.abs(Dbuf[rit].double().cpu().numpy() - Dref) / rscale))
     eps_ratio_v = float(np.max(np.abs(Rbuf[rit].double().cpu().numpy() - Dref[:, 0]) / sv))
-    del s32, rows_d, Dbuf, Rbuf, rows_np
+    # Sherman-Morrison update after one accepted move per walker: the 512
+    # stacked 384 x 384 FP32 inverses above (their rows stand in for A^-1),
+    # electron k_w = w mod 384, unit-variance orbital values.
+    n_w = B // N
+    inv_d = rows_d.view(n_w, N, N)
+    k_d = torch.arange(n_w, dtype=torch.int32, device=dev) % N
+    phi_d = torch.from_numpy(W.make_inverse_rows(3, n_w, N, seed=33) * np.float32(np.sqrt(N))).to(dev)
+    ms_sm, _ = time_steps(torch, lambda: q.det_update(inv_d, k_d, phi_d), args.steps, args.warmup)
+    bytes_sm = n_w * (8.0 * N * N + 4 * N + 4)
+    del s32, rows_d, Dbuf, Rbuf, rows_np, inv_d, phi_d
     torch.cuda.empty_cache()
     bpu_rvgl = 64 * 4 + 4 + 20.0 / N
     bpu_rv = 64 * 4 + 4 + 4.0 / N
@@ -297,6 +306,9 @@ def main() -> int:
                                "bytes_per_unit": bpu_rvgl, "speedup_vs_f32_vgl": ms32 / ms_rvgl,
                                "eps": eps_ratio,
                                "traffic": traffic_from_profiles(tile32, "ratio_vgl_f32_80cube_n384")},
+             "f32_det_update": {"walkers": B // N, "n": N, "ms_per_step": ms_sm,
+                                "updates_per_s": (B // N) / (ms_sm * 1e-3), "bytes_per_update": bytes_sm / (B // N),
+                                "hbm_frac": bytes_sm / (ms_sm * 1e-3) / 1e9 / PEAK_HBM_GBS},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}

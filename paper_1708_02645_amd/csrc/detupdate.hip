@@ -99,35 +99,54 @@ __global__ __launch_bounds__(kSmThreads) void sm_rows_kernel(SmArgs a)
     const int r1 = min(n, r0 + a.rows_per_group);
     using V = typename Vec16<T>::type;
     constexpr int VN = Vec16<T>::n;
-    for (int i = r0 + wave; i < r1; i += kSmThreads / 64) {
-        if (i == k) continue;
-        T* Ai = A + (int64_t)i * n;
-        if constexpr (C > 0) {
-            V x[C];
-            T s = T(0);
+    constexpr int NW = kSmThreads / 64;
+    if constexpr (C > 0) {
+        // two rows per wave in flight: loads of both, then both reductions
+        for (int i0 = r0 + wave; i0 < r1; i0 += 2 * NW) {
+            const int rows[2] = {i0, i0 + NW};
+            V x[2][C];
+            T s[2] = {T(0), T(0)};
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int j = (c * 64 + lane) * VN;
-                if (j < n) x[c] = *reinterpret_cast<const V*>(Ai + j);
-            }
+            for (int r = 0; r < 2; ++r) {
+                if (rows[r] >= r1 || rows[r] == k) continue;
+                const T* Ai = A + (int64_t)rows[r] * n;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int j = (c * 64 + lane) * VN;
-                if (j < n)
-#pragma unroll
-                    for (int e = 0; e < VN; ++e) s = fma(x[c][e], phs[j + e], s);
-            }
-            const T coef = wave_sum(s) * inv_rho;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int j = (c * 64 + lane) * VN;
-                if (j < n) {
-#pragma unroll
-                    for (int e = 0; e < VN; ++e) x[c][e] = fma(-coef, rks[j + e], x[c][e]);
-                    *reinterpret_cast<V*>(Ai + j) = x[c];
+                for (int c = 0; c < C; ++c) {
+                    const int j = (c * 64 + lane) * VN;
+                    if (j < n) x[r][c] = *reinterpret_cast<const V*>(Ai + j);
                 }
             }
-        } else {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int j = (c * 64 + lane) * VN;
+                    if (j < n && rows[r] < r1 && rows[r] != k)
+#pragma unroll
+                        for (int e = 0; e < VN; ++e) s[r] = fma(x[r][c][e], phs[j + e], s[r]);
+                }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const T coef = wave_sum(s[r]) * inv_rho;  // every lane of the wave takes part
+                if (rows[r] >= r1 || rows[r] == k) continue;
+                T* Ai = A + (int64_t)rows[r] * n;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int j = (c * 64 + lane) * VN;
+                    if (j < n) {
+#pragma unroll
+                        for (int e = 0; e < VN; ++e) x[r][c][e] = fma(-coef, rks[j + e], x[r][c][e]);
+                        *reinterpret_cast<V*>(Ai + j) = x[r][c];
+                    }
+                }
+            }
+        }
+        return;
+    }
+    for (int i = r0 + wave; i < r1; i += NW) {
+        if (i == k) continue;
+        T* Ai = A + (int64_t)i * n;
+        {
             T s = T(0);
             for (int j = lane; j < n; j += 64) s = fma(Ai[j], phs[j], s);
             const T coef = wave_sum(s) * inv_rho;
