@@ -185,3 +185,59 @@ def make_inverse_rows(k: int, count: int, norb: int, seed: int | None = None, dt
         out[i:j] = r.standard_normal((j - i, norb), dtype=np.float64 if dtype == np.float64 else np.float32)
     out *= np.asarray(1.0 / np.sqrt(norb), dtype=dtype)
     return out
+
+
+# Jastrow workload (J1 + J2 with 1D cubic B-spline functors), seeded by
+# SeedSequence(6): stream 0 functor coefficients, stream 1 electron
+# positions, stream 2 proposed moves and moved electrons.
+JASTROW = dict(cell=(1.0, 1.0, 1.0), n_elec=384, n_up=192, ion_grid=4, intervals=8, rcut=0.5, walkers=512)
+
+
+def make_jastrow(seed: int = 6, n_elec: int | None = None, n_up: int | None = None, intervals: int | None = None,
+                 rcut: float | None = None, cell=None):
+    """Ions, species and functors of the Jastrow workload.
+
+    32 ions on the sites of a 4x4x4 grid with even index sum (an fcc
+    arrangement in the unit cube, as in a rock-salt oxide's cation or anion
+    sublattice), two species alternating with the x index (the paper's NiO:
+    Ni and O); n_elec electrons, the first n_up spin up.  Functors: M
+    intervals on [0, rcut), the last three coefficients zero (U, U', U''
+    vanish at the cutoff), the others a decaying cubic profile of seeded
+    amplitude.  Returns dict(cell, ions, species, f1=[(c, rcut)]*2, uu, ud,
+    n_elec, n_up)."""
+    w = JASTROW
+    cell = tuple(cell or w["cell"])
+    n_elec = n_elec or w["n_elec"]
+    n_up = n_elec // 2 if n_up is None else n_up
+    M = intervals or w["intervals"]
+    rcut = rcut or w["rcut"]
+    r = rngs(6, seed)[0]
+    g = w["ion_grid"]
+    sites = [(i, j, k) for i in range(g) for j in range(g) for k in range(g) if (i + j + k) % 2 == 0]
+    ions = (np.array(sites, dtype=np.float64) + 0.5) / g * np.asarray(cell)
+    species = np.array([s[0] % 2 for s in sites], dtype=np.int32)
+
+    def profile(amp):
+        x = np.arange(M + 3, dtype=np.float64)
+        c = amp * np.clip(1.0 - (x - 1.0) / M, 0.0, None) ** 3 * (1.0 + 0.1 * r.uniform(-1, 1, size=M + 3))
+        c[M:] = 0.0
+        return c
+
+    f1 = [(profile(-1.5), rcut), (profile(-0.8), rcut)]
+    uu = (profile(-0.25), rcut)
+    ud = (profile(-0.5), rcut)
+    return dict(cell=cell, ions=ions, species=species, f1=f1, uu=uu, ud=ud, n_elec=n_elec, n_up=n_up)
+
+
+def make_electrons(walkers: int, n_elec: int, seed: int = 6, cell=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """[walkers][n_elec][3] uniform positions in the cell."""
+    r = rngs(6, seed)[1]
+    return r.random((walkers, n_elec, 3)) * np.asarray(cell)
+
+
+def make_moves(walkers: int, n_elec: int, step: float = 0.05, seed: int = 6):
+    """(k[walkers] int32, displacement[walkers][3]): one proposed move per
+    walker, a Gaussian step of standard deviation `step` per coordinate."""
+    r = rngs(6, seed)[2]
+    k = r.integers(0, n_elec, size=walkers).astype(np.int32)
+    return k, r.normal(scale=step, size=(walkers, 3))
