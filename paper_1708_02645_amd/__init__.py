@@ -64,6 +64,13 @@ def lib():
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
             "spline_eval_ratio_vgl": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
             "spline_det_update": ([p, i32, i64, p, p, p, i64, i64, ctypes.c_int, p], ctypes.c_int),
+            "jastrow_bytes": ([p, p], sz),
+            "jastrow_create": ([p, p, p, p, p, p, p, sz, p, p], ctypes.c_int),
+            "jastrow_destroy": ([p], ctypes.c_int),
+            "jastrow_move": ([p, p, i64, i64, p, p, p, i64, p, p], ctypes.c_int),
+            "jastrow_evaluate": ([p, p, i64, i64, i64, p, p, p, p], ctypes.c_int),
+            "jastrow_dist_rows": ([p, p, i64, i64, p, p, i64, p, p, p, p, p], ctypes.c_int),
+            "jastrow_accept": ([p, p, i64, i64, p, p, p, i64, p], ctypes.c_int),
             "spline_set_lattice": ([p, p], ctypes.c_int),
             "spline_get_lattice": ([p, p], ctypes.c_int),
             "spline_eval_vgh": ([p, p, i64, p, p, p, p], ctypes.c_int),
@@ -715,6 +722,148 @@ class SurrogateMLP:
         if getattr(self, "_h", None) is not None and self._h.value:
             _mlp_lib().spline_mlp_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class JastrowDesc(ctypes.Structure):
+    _fields_ = [("n_elec", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_ion", ctypes.c_int32),
+                ("n_species", ctypes.c_int32), ("cell", ctypes.c_double * 3)]
+
+
+class Jastrow:
+    """One- and two-body Jastrow factor on a GPU (include/qmcjastrow.h).
+
+    f1: one (coefs, rcut) per ion species; uu / ud: the two-body functors for
+    equal and opposite spins.  Electron positions are float32 tensors
+    [W, 3, ld] (structure of arrays; ``positions`` converts [W, N, 3])."""
+
+    def __init__(self, cell, ions, species, f1, uu, ud, n_elec, n_up, device="cuda", stream=None):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        ions = np.ascontiguousarray(ions, dtype=np.float64).reshape(-1, 3)
+        species = np.ascontiguousarray(species, dtype=np.int32).reshape(-1)
+        funs = list(f1) + [uu, ud]
+        self.n_elec, self.n_up, self.n_ion = int(n_elec), int(n_up), ions.shape[0]
+        self.desc = JastrowDesc(self.n_elec, self.n_up, self.n_ion, len(f1), (ctypes.c_double * 3)(*cell))
+        iv = np.array([len(c) - 3 for c, _ in funs], dtype=np.int32)
+        rc = np.array([float(r) for _, r in funs], dtype=np.float64)
+        cf = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64) for c, _ in funs]))
+        L = lib()
+        nb = L.jastrow_bytes(ctypes.byref(self.desc), iv.ctypes.data)
+        if nb == 0:
+            raise SplineError(-1, "invalid Jastrow sizes or cell")
+        self.buf = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(torch, self.device, stream)
+            check(L.jastrow_create(ctypes.byref(self.desc), ions.ctypes.data if self.n_ion else None,
+                                   species.ctypes.data if self.n_ion else None, iv.ctypes.data, rc.ctypes.data,
+                                   cf.ctypes.data, ctypes.c_void_p(self.buf.data_ptr()), nb, sp, ctypes.byref(h)))
+        self._h = h
+        self.ld = (self.n_elec + 63) // 64 * 64
+
+    def positions(self, R):
+        """[W, N, 3] array -> float32 [W, 3, ld] device tensor (padding zero)."""
+        R = np.asarray(R, dtype=np.float64)
+        out = np.zeros((R.shape[0], 3, self.ld), dtype=np.float32)
+        out[:, :, :self.n_elec] = np.transpose(R, (0, 2, 1))
+        return self._torch.from_numpy(out).to(self.device)
+
+    def _R(self, R):
+        t = self._torch
+        if not (isinstance(R, t.Tensor) and R.dtype == t.float32 and R.device == self.device and R.dim() == 3
+                and R.shape[1] == 3 and R.shape[2] >= self.n_elec and R.is_contiguous()):
+            raise ValueError("R must be a contiguous float32 [W, 3, >=n_elec] tensor on %s" % self.device)
+        return R, R.shape[2], 3 * R.shape[2]
+
+    def _slots(self, R, k, r, walkers):
+        t = self._torch
+        count = k.shape[0]
+        if not (isinstance(k, t.Tensor) and k.dtype == t.int32 and k.device == self.device and k.is_contiguous()):
+            raise ValueError("k must be a contiguous int32 tensor on %s" % self.device)
+        if not (isinstance(r, t.Tensor) and r.dtype == t.float64 and r.device == self.device and r.is_contiguous()
+                and tuple(r.shape) == (count, 3)):
+            raise ValueError("positions must be a contiguous float64 [count, 3] tensor on %s" % self.device)
+        if walkers is not None:
+            if not (isinstance(walkers, t.Tensor) and walkers.dtype == t.int32 and walkers.device == self.device
+                    and walkers.is_contiguous() and tuple(walkers.shape) == (count,)):
+                raise ValueError("walkers must be a contiguous int32 [count] tensor on %s" % self.device)
+            if count and (int(walkers.min().item()) < 0 or int(walkers.max().item()) >= R.shape[0]):
+                raise ValueError("walker index out of range")
+        elif count > R.shape[0]:
+            raise ValueError("more slots than walkers")
+        return count
+
+    @staticmethod
+    def _p(x):
+        return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+    def move(self, R, k, rnew, walkers=None, out=None, stream=None):
+        """[count, 5] float32: Delta J, grad_k J (x, y, z), lap_k J for moving
+        electron k[s] of walker walkers[s] (or s) to rnew[s]."""
+        t = self._torch
+        R, ld, ws = self._R(R)
+        count = self._slots(R, k, rnew, walkers)
+        out = out if out is not None else t.empty((count, 5), dtype=t.float32, device=self.device)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().jastrow_move(self._h, self._p(R), ld, ws, self._p(walkers), self._p(k), self._p(rnew), count,
+                                     self._p(out), sp))
+        return out
+
+    def evaluate(self, R, out=None, stream=None):
+        """(J [W], G [W, 3, N], L [W, N]) float32."""
+        t = self._torch
+        R, ld, ws = self._R(R)
+        W_ = R.shape[0]
+        kw = dict(dtype=t.float32, device=self.device)
+        J, G, L = out if out is not None else (t.empty(W_, **kw), t.empty((W_, 3, self.n_elec), **kw),
+                                               t.empty((W_, self.n_elec), **kw))
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().jastrow_evaluate(self._h, self._p(R), ld, ws, W_, self._p(J), self._p(G), self._p(L), sp))
+        return J, G, L
+
+    def dist_rows(self, R, r, walkers=None, stream=None):
+        """(de [c, N], dre [c, 3, N], di [c, n_ion], dri [c, 3, n_ion]) with
+        dr = r_other - r (minimum image)."""
+        t = self._torch
+        R, ld, ws = self._R(R)
+        dummy_k = t.zeros(r.shape[0], dtype=t.int32, device=self.device)
+        count = self._slots(R, dummy_k, r, walkers)
+        kw = dict(dtype=t.float32, device=self.device)
+        de, dre = t.empty((count, self.n_elec), **kw), t.empty((count, 3, self.n_elec), **kw)
+        di, dri = t.empty((count, self.n_ion), **kw), t.empty((count, 3, self.n_ion), **kw)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().jastrow_dist_rows(self._h, self._p(R), ld, ws, self._p(walkers), self._p(r), count,
+                                          self._p(de), self._p(dre), self._p(di) if self.n_ion else None,
+                                          self._p(dri) if self.n_ion else None, sp))
+        return de, dre, di, dri
+
+    def accept(self, R, k, rnew, walkers=None, stream=None):
+        t = self._torch
+        R, ld, ws = self._R(R)
+        count = self._slots(R, k, rnew, walkers)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().jastrow_accept(self._h, self._p(R), ld, ws, self._p(walkers), self._p(k), self._p(rnew),
+                                       count, sp))
+        return R
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().jastrow_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

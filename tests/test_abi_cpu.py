@@ -16,9 +16,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "qmcspline.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(spline_\w+)\s*\(", txt)))
+    names = set()
+    for h in ("qmcspline.h", "qmcjastrow.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b((?:spline|jastrow)_\w+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_header_symbol():
@@ -155,3 +158,21 @@ def test_det_update_rejects_bad_arguments_without_a_gpu():
     assert L.spline_det_update(None, 4, 16, None, None, None, 4, 0, 1, None) == 0  # empty: no-op
     assert L.spline_det_update(None, 4, 16, None, None, None, 4, 1, 1, None) == -1
     assert L.spline_det_update(None, 4, 16, None, None, None, 4, -1, 1, None) == -1
+
+
+def test_jastrow_sizes_and_argument_checks_without_a_gpu():
+    import ctypes
+
+    L = q.lib()
+    d = q.JastrowDesc(384, 192, 32, 2, (ctypes.c_double * 3)(1.0, 1.0, 1.0))
+    iv = np.array([8, 8, 8, 8], dtype=np.int32)
+    nb = L.jastrow_bytes(ctypes.byref(d), iv.ctypes.data)
+    assert nb > 0 and nb % 256 == 0
+    bad = q.JastrowDesc(384, 400, 32, 2, (ctypes.c_double * 3)(1.0, 1.0, 1.0))  # n_up > n_elec
+    assert L.jastrow_bytes(ctypes.byref(bad), iv.ctypes.data) == 0
+    iv0 = np.array([8, 0, 8, 8], dtype=np.int32)
+    assert L.jastrow_bytes(ctypes.byref(d), iv0.ctypes.data) == 0
+    for fn, args in ((L.jastrow_move, (None, None, 384, 3 * 384, None, None, None, 1, None, None)),
+                     (L.jastrow_evaluate, (None, None, 384, 3 * 384, 1, None, None, None, None)),
+                     (L.jastrow_accept, (None, None, 384, 3 * 384, None, None, None, 1, None))):
+        assert fn(*args) == -1 and "handle" in q.last_error()

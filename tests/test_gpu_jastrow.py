@@ -1,0 +1,197 @@
+"""GPU parity of the Jastrow kernels (include/qmcjastrow.h) against the FP64
+oracle (oracle/jastrow.py).
+
+Error measure: |gpu - ref| / scale, where the scale is the sum of the
+absolute pair terms that enter the quantity (sum |U| over the new and old
+positions for Delta J; sum |U'| for a gradient component; sum |U''| +
+2|U'|/d for a Laplacian): FP32 rounding of the positions, distances and of
+each term is relative to its own size, so the error of a sum is bounded by
+a few units in the last place times this scale.  Bar: 1e-5 (FP32), with the
+positions themselves stored in FP32.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def q(torch):
+    import paper_1708_02645_amd as qq
+    qq.lib()
+    return qq
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _make(q, n_elec=None, **kw):
+    from oracle import jastrow as oj
+
+    d = W.make_jastrow(n_elec=n_elec, **kw)
+    J = q.Jastrow(d["cell"], d["ions"], d["species"], d["f1"], d["uu"], d["ud"], d["n_elec"], d["n_up"])
+    S = oj.System(d["cell"], d["ions"], d["species"], d["f1"], d["uu"], d["ud"], d["n_up"])
+    return J, S, d
+
+
+def _abs_terms(S, R, k, r):
+    """(sum |U|, sum |U'|, sum |U''| + 2|U'|/d) of the pair terms of electron
+    k placed at r."""
+    from oracle import jastrow as oj
+
+    de, dre, di, dri = S.rows(R, r)
+    others = np.array([i for i in range(len(R)) if i != k])
+    same = S._same_spin(k, others)
+    tot = np.zeros(3)
+    for sel, (c, rc) in ((same, S.uu), (~same, S.ud)):
+        u, du, d2u = oj.functor(de[others][sel], c, rc)
+        dd = np.maximum(de[others][sel], 1e-30)
+        tot += [np.abs(u).sum(), np.abs(du).sum(), (np.abs(d2u) + 2 * np.abs(du) / dd).sum()]
+    for s, (c, rc) in enumerate(S.f1):
+        sel = S.species == s
+        u, du, d2u = oj.functor(di[sel], c, rc)
+        dd = np.maximum(di[sel], 1e-30)
+        tot += [np.abs(u).sum(), np.abs(du).sum(), (np.abs(d2u) + 2 * np.abs(du) / dd).sum()]
+    return tot
+
+
+def _f32(R):
+    return np.asarray(R, dtype=np.float32).astype(np.float64)
+
+
+def _check_moves(S, R, ks, rnew, walkers, out, what):
+    worst = 0.0
+    for s in range(len(ks)):
+        w, k = int(walkers[s]), int(ks[s])
+        Rw = _f32(R[w])
+        rn = _f32(rnew[s])
+        dJ, g, lap = S.move(Rw, k, rn)
+        a_new = _abs_terms(S, Rw, k, rn)
+        a_old = _abs_terms(S, Rw, k, Rw[k])
+        scale = np.array([a_new[0] + a_old[0], a_new[1], a_new[1], a_new[1], a_new[2]])
+        ref = np.array([dJ, g[0], g[1], g[2], lap])
+        worst = max(worst, float(np.max(np.abs(out[s] - ref) / scale)))
+    _say("%s: worst err %.2e" % (what, worst))
+    assert worst <= TOL
+
+
+def test_small_system_every_electron(torch, q):
+    J, S, d = _make(q, n_elec=12, n_up=5)
+    Wn, N = 6, 12
+    R = W.make_electrons(Wn, N)
+    Rd = J.positions(R)
+    walkers = np.repeat(np.arange(Wn), N).astype(np.int32)
+    ks = np.tile(np.arange(N), Wn).astype(np.int32)
+    rng = np.random.default_rng(5)
+    rnew = R[walkers, ks] + rng.normal(scale=0.05, size=(Wn * N, 3))
+    out = J.move(Rd, torch.from_numpy(ks).cuda(), torch.from_numpy(rnew).cuda(),
+                 walkers=torch.from_numpy(walkers).cuda()).cpu().numpy()
+    _check_moves(S, R, ks, rnew, walkers, out, "small moves")
+
+
+def test_full_workload_moves_sampled(torch, q):
+    """384 electrons, 32 ions, 512 walkers, one proposed move each (the
+    benchmark's batch); the oracle checks 24 slots."""
+    J, S, d = _make(q)
+    Wn, N = W.JASTROW["walkers"], d["n_elec"]
+    R = W.make_electrons(Wn, N)
+    ks, disp = W.make_moves(Wn, N)
+    rnew = R[np.arange(Wn), ks] + disp
+    out = J.move(J.positions(R), torch.from_numpy(ks).cuda(), torch.from_numpy(rnew).cuda()).cpu().numpy()
+    idx = np.concatenate([np.random.default_rng(0).choice(Wn, 22, replace=False), [0, Wn - 1]])
+    _check_moves(S, R, ks[idx], rnew[idx], idx, out[idx], "full moves")
+
+
+@pytest.mark.parametrize("n_elec,n_up", [(12, 5), (64, 32), (97, 40)])
+def test_evaluate_against_oracle(torch, q, n_elec, n_up):
+    J, S, d = _make(q, n_elec=n_elec, n_up=n_up)
+    Wn = 3
+    R = W.make_electrons(Wn, n_elec)
+    Jg, Gg, Lg = (t.cpu().numpy().astype(np.float64) for t in J.evaluate(J.positions(R)))
+    for w in range(Wn):
+        Jr, Gr, Lr = S.evaluate(_f32(R[w]))
+        sc = [_abs_terms(S, _f32(R[w]), i, _f32(R[w][i])) for i in range(n_elec)]
+        sv = sum(s[0] for s in sc)  # bounds |J|'s terms (each pair appears twice here)
+        assert abs(Jg[w] - Jr) <= TOL * sv, (w, Jg[w], Jr)
+        for i in range(n_elec):
+            assert np.all(np.abs(Gg[w, :, i] - Gr[i]) <= TOL * sc[i][1]), (w, i)
+            assert abs(Lg[w, i] - Lr[i]) <= TOL * sc[i][2], (w, i)
+    _say("evaluate n=%d ok" % n_elec)
+
+
+def test_full_workload_evaluate_sampled(torch, q):
+    J, S, d = _make(q)
+    Wn, N = 64, d["n_elec"]
+    R = W.make_electrons(Wn, N)
+    Jg, Gg, Lg = (t.cpu().numpy().astype(np.float64) for t in J.evaluate(J.positions(R)))
+    for w in (0, Wn - 1):
+        Jr, Gr, Lr = S.evaluate(_f32(R[w]))
+        sc = np.array([_abs_terms(S, _f32(R[w]), i, _f32(R[w][i])) for i in range(N)])
+        assert abs(Jg[w] - Jr) <= TOL * sc[:, 0].sum()
+        assert np.all(np.abs(Gg[w].T - Gr) <= TOL * sc[:, 1:2])
+        assert np.all(np.abs(Lg[w] - Lr) <= TOL * sc[:, 2])
+    _say("full evaluate ok: J[0] = %.6f" % Jg[0])
+
+
+def test_dist_rows_and_accept_consistency(torch, q):
+    J, S, d = _make(q, n_elec=64, n_up=32)
+    Wn, N = 5, 64
+    R = W.make_electrons(Wn, N)
+    Rd = J.positions(R)
+    rng = np.random.default_rng(2)
+    r = rng.random((Wn, 3)) * 1.5 - 0.25
+    de, dre, di, dri = (t.cpu().numpy().astype(np.float64) for t in J.dist_rows(Rd, torch.from_numpy(r).cuda()))
+    for w in range(Wn):
+        e, er, i_, ir = S.rows(_f32(R[w]), _f32(r[w]))
+        np.testing.assert_allclose(de[w], e, atol=1e-6)
+        np.testing.assert_allclose(dre[w].T, er, atol=1e-6)
+        np.testing.assert_allclose(di[w], i_, atol=1e-6)
+        np.testing.assert_allclose(dri[w].T, ir, atol=1e-6)
+    # accept: J after minus J before equals the move's Delta J
+    ks = np.array([3, 40, 0, 63, 17], dtype=np.int32)
+    rnew = R[np.arange(Wn), ks] + rng.normal(scale=0.05, size=(Wn, 3))
+    kd, rd = torch.from_numpy(ks).cuda(), torch.from_numpy(rnew).cuda()
+    mv = J.move(Rd, kd, rd).cpu().numpy().astype(np.float64)
+    J0 = J.evaluate(Rd)[0].cpu().numpy().astype(np.float64)
+    J.accept(Rd, kd, rd)
+    J1 = J.evaluate(Rd)[0].cpu().numpy().astype(np.float64)
+    for w in range(Wn):
+        sc = _abs_terms(S, _f32(R[w]), int(ks[w]), _f32(rnew[w]))[0] + _abs_terms(S, _f32(R[w]), int(ks[w]),
+                                                                                  _f32(R[w][ks[w]]))[0]
+        assert abs((J1[w] - J0[w]) - mv[w, 0]) <= 4 * TOL * (sc + abs(J0[w]))
+    R2 = Rd.cpu().numpy()
+    np.testing.assert_array_equal(R2[np.arange(Wn), :, ks], rnew.astype(np.float32))
+
+
+def test_edges(torch, q):
+    J, S, d = _make(q, n_elec=16, n_up=8)
+    R = W.make_electrons(2, 16)
+    Rd = J.positions(R)
+    kd = torch.tensor([3, 99], dtype=torch.int32, device="cuda")
+    rd = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    out = J.move(Rd, kd, rd).cpu().numpy()
+    assert np.all(np.isfinite(out[0])) and np.all(np.isnan(out[1]))
+    e = J.move(Rd, kd[:0], rd[:0])
+    assert tuple(e.shape) == (0, 5)
+    # an electron placed exactly on an ion: finite value, derivative terms skipped
+    ion = np.asarray(d["ions"][0])
+    out = J.move(Rd, kd[:1], torch.from_numpy(ion[None].astype(np.float32).astype(np.float64)).cuda()).cpu().numpy()
+    ref = S.move(_f32(R[0]), 3, _f32(ion))
+    assert np.all(np.isfinite(out)) and abs(out[0, 0] - ref[0]) < 1e-4
+    with pytest.raises(q.SplineError):
+        q.Jastrow((1.0, 1.0, 1.0), d["ions"], d["species"], [(d["f1"][0][0], 0.7)] * 2, d["uu"], d["ud"], 16, 8)
