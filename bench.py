@@ -370,6 +370,53 @@ def main() -> int:
         "hbm_frac": units * BYTES_PER_UNIT["f32"] / (ms_vgl_hex * 1e-3) / 1e9 / PEAK_HBM_GBS}
     log("bench: vgh %.3f ms, vgh hexagonal %.3f ms, vgl hexagonal %.3f ms" % (ms_vgh, ms_vgh_hex, ms_vgl_hex))
 
+    # Jastrow (J1 + J2, 1D cubic B-spline functors): 384 electrons, 32 ions,
+    # one proposed move per walker (512 and 16384 walkers), and the full
+    # evaluation of 512 walkers.  Pair evaluations: a move forms every pair
+    # of the moved electron at its old and new position.
+    log("bench: Jastrow ...")
+    jd = W.make_jastrow()
+    jas = q.Jastrow(jd["cell"], jd["ions"], jd["species"], jd["f1"], jd["uu"], jd["ud"], jd["n_elec"], jd["n_up"],
+                    device=dev)
+    NE, NI = jd["n_elec"], len(jd["ions"])
+    jforms = {}
+    for nw in (W.JASTROW["walkers"], 16384):
+        Re = W.make_electrons(nw, NE)
+        Rd = jas.positions(Re)
+        ks, disp = W.make_moves(nw, NE)
+        kd = torch.from_numpy(ks).to(dev)
+        rd = torch.from_numpy(Re[np.arange(nw), ks] + disp).to(dev)
+        jout = torch.empty((nw, 5), dtype=torch.float32, device=dev)
+        ms_mv, _ = time_steps(torch, lambda: jas.move(Rd, kd, rd, out=jout), args.steps, args.warmup)
+        pairs = nw * 2 * (NE - 1 + NI)
+        jforms["move_%d_walkers" % nw] = {"ms_per_step": ms_mv, "pair_evals_per_s": pairs / (ms_mv * 1e-3),
+                                          "moves_per_s": nw / (ms_mv * 1e-3)}
+        if nw == W.JASTROW["walkers"]:
+            jo = (torch.empty(nw, dtype=torch.float32, device=dev),
+                  torch.empty((nw, 3, NE), dtype=torch.float32, device=dev),
+                  torch.empty((nw, NE), dtype=torch.float32, device=dev))
+            ms_ev, _ = time_steps(torch, lambda: jas.evaluate(Rd, out=jo), args.steps, args.warmup)
+            pairs_ev = nw * NE * (NE - 1 + NI)
+            jforms["evaluate_%d_walkers" % nw] = {"ms_per_step": ms_ev, "pair_evals_per_s": pairs_ev / (ms_ev * 1e-3)}
+            del jo
+        del Re, Rd, jout
+    jforms["system"] = "%d electrons (%d up), %d ions of 2 species, unit cube, functors with 8 intervals, rcut 0.5" % (
+        NE, jd["n_up"], NI)
+    # ALU roofline: FP32 operations of the definition per pair term (58 with
+    # derivatives, 35 for a value only; DESIGN lists them) against the VALU
+    # issue rate, 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (packed FP32 off).
+    peak_ops = 256 * 4 * 16 * 2.4e9
+    for key, v in jforms.items():
+        if not isinstance(v, dict):
+            continue
+        ops = 58.0 if key.startswith("evaluate") else (58.0 + 35.0) / 2
+        v["roofline"] = {"bound": "alu", "ops_per_pair": ops, "achieved_Tops": v["pair_evals_per_s"] * ops / 1e12,
+                         "peak_Tops": peak_ops / 1e12, "frac": v["pair_evals_per_s"] * ops / peak_ops}
+    forms["jastrow_f32"] = jforms
+    log("bench: jastrow %s" % {k: round(v["ms_per_step"], 4) for k, v in jforms.items() if isinstance(v, dict)})
+    del jas
+    torch.cuda.empty_cache()
+
     if not args.no_ragged:
         # Ragged workload: four tables (32^3/48^3/64^3/80^3, N = 64/128/256/384,
         # FP32) with U{64..1024} walkers each, in one graph-captured

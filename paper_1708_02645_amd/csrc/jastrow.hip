@@ -79,44 +79,89 @@ __device__ inline void j_stage(const JArgs& a, unsigned char* lds, JStage& st)
 
 __device__ inline float min_image(float d, float L, float Linv) { return d - L * rintf(d * Linv); }
 
-// U, U', U'' of functor f at distance r (0 beyond the cutoff).
-__device__ inline void functor(const JFun& f, const float* coefs, float r, float& u, float& du, float& d2u)
+// Basis of functor f at distance r: first coefficient and cubic weights.
+// Branch-free: beyond the cutoff the interval index is clamped and `inside`
+// is false (the caller zeroes the terms).
+struct FBasis {
+    const float* c;
+    float x, s;
+    bool inside;
+};
+
+__device__ inline FBasis fbasis(const JFun& f, const float* coefs, float r)
 {
-    if (!(r < f.rcut)) {
-        u = du = d2u = 0.f;
-        return;
-    }
+    FBasis b;
     const float t = r * f.hinv;
     int i = (int)t;
     i = i > f.m - 1 ? f.m - 1 : i;
-    const float x = t - (float)i;
-    const float s = 1.f - x, x2 = x * x;
-    const float* c = coefs + f.off + i;
-    const float c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
-    const float b0 = s * s * s * (1.f / 6.f), b1 = 2.f / 3.f + x2 * (0.5f * x - 1.f);
-    const float b2 = 1.f / 6.f + 0.5f * (x + x2 - x2 * x), b3 = x2 * x * (1.f / 6.f);
-    u = b0 * c0 + b1 * c1 + b2 * c2 + b3 * c3;
-    // derivatives from differences of the coefficients (quadratic and linear B-splines)
-    const float d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
-    du = f.hinv * (0.5f * s * s * d0 + (0.5f + x - x2) * d1 + 0.5f * x2 * d2);
-    d2u = f.hinv * f.hinv * (s * (d1 - d0) + x * (d2 - d1));
+    b.x = t - (float)i;
+    b.s = 1.f - b.x;
+    b.c = coefs + f.off + i;
+    b.inside = r < f.rcut;
+    return b;
 }
 
-// Adds the pair term of electron e at (dx, dy, dz) = r_e - r_other.
+// U only.
+__device__ inline float fvalue(const JFun& f, const float* coefs, float r)
+{
+    const FBasis b = fbasis(f, coefs, r);
+    const float x = b.x, s = b.s, x2 = x * x;
+    const float u = (s * s * s) * (1.f / 6.f) * b.c[0] + (2.f / 3.f + x2 * (0.5f * x - 1.f)) * b.c[1] +
+                    (1.f / 6.f + 0.5f * (x + x2 - x2 * x)) * b.c[2] + (x2 * x) * (1.f / 6.f) * b.c[3];
+    return b.inside ? u : 0.f;
+}
+
+// U, U', U'' (derivatives from differences of the coefficients: the
+// quadratic and linear B-splines of first and second differences).
+__device__ inline void functor(const JFun& f, const float* coefs, float r, float& u, float& du, float& d2u)
+{
+    const FBasis b = fbasis(f, coefs, r);
+    const float x = b.x, s = b.s, x2 = x * x;
+    const float c0 = b.c[0], c1 = b.c[1], c2 = b.c[2], c3 = b.c[3];
+    const float v = (s * s * s) * (1.f / 6.f) * c0 + (2.f / 3.f + x2 * (0.5f * x - 1.f)) * c1 +
+                    (1.f / 6.f + 0.5f * (x + x2 - x2 * x)) * c2 + (x2 * x) * (1.f / 6.f) * c3;
+    const float d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
+    const float g = f.hinv * (0.5f * s * s * d0 + (0.5f + x - x2) * d1 + 0.5f * x2 * d2);
+    const float h = f.hinv * f.hinv * (s * (d1 - d0) + x * (d2 - d1));
+    u = b.inside ? v : 0.f;
+    du = b.inside ? g : 0.f;
+    d2u = b.inside ? h : 0.f;
+}
+
+// Distance and its reciprocal from a displacement (hardware reciprocal
+// square root; 0 and 0 for a zero displacement).
+__device__ inline float pair_dist(float dx, float dy, float dz, float& rinv)
+{
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float ri = __builtin_amdgcn_rsqf(d2);
+    const bool nz = d2 > 0.f;
+    rinv = nz ? ri : 0.f;
+    return nz ? d2 * ri : 0.f;
+}
+
+// Adds the pair term of electron e at (dx, dy, dz) = r_e - r_other: U to v,
+// U' (dx, dy, dz) / d to the gradient and U'' + 2 U' / d to the Laplacian
+// (a zero distance adds U(0) only).
 __device__ inline void pair_terms(const JFun& f, const float* coefs, float dx, float dy, float dz, float& v,
                                   float& gx, float& gy, float& gz, float& lap)
 {
-    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+    float rinv;
+    const float d = pair_dist(dx, dy, dz, rinv);
     float u, du, d2u;
     functor(f, coefs, d, u, du, d2u);
     v += u;
-    if (d > 0.f) {
-        const float q = du / d;
-        gx = fmaf(q, dx, gx);
-        gy = fmaf(q, dy, gy);
-        gz = fmaf(q, dz, gz);
-        lap += d2u + 2.f * q;
-    }
+    const float q = du * rinv;
+    gx = fmaf(q, dx, gx);
+    gy = fmaf(q, dy, gy);
+    gz = fmaf(q, dz, gz);
+    lap += (rinv > 0.f ? d2u : 0.f) + 2.f * q;
+}
+
+// U of the pair at (dx, dy, dz).
+__device__ inline float pair_value(const JFun& f, const float* coefs, float dx, float dy, float dz)
+{
+    float rinv;
+    return fvalue(f, coefs, pair_dist(dx, dy, dz, rinv));
 }
 
 __device__ inline float wave_sum(float x)
@@ -166,20 +211,20 @@ __global__ __launch_bounds__(kJThreads) void jastrow_move_kernel(MoveArgs a)
         if (i == k) continue;
         const float xi = Rx[i], yi = Ry[i], zi = Rz[i];
         const JFun& f = ((i < a.j.n_up) == up_k) ? fsame : fdiff;
-        float vn = 0.f, vo = 0.f, t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+        float vn = 0.f;
         pair_terms(f, st.coefs, min_image(xn - xi, L0, I0), min_image(yn - yi, L1, I1), min_image(zn - zi, L2, I2),
                    vn, gx, gy, gz, lap);
-        pair_terms(f, st.coefs, min_image(xo - xi, L0, I0), min_image(yo - yi, L1, I1), min_image(zo - zi, L2, I2),
-                   vo, t0, t1, t2, t3);
+        const float vo = pair_value(f, st.coefs, min_image(xo - xi, L0, I0), min_image(yo - yi, L1, I1),
+                                    min_image(zo - zi, L2, I2));
         dv += vn - vo;
     }
     for (int I = lane; I < a.j.n_ion; I += 64) {
         const JFun& f = st.fun[st.isp[I]];
-        float vn = 0.f, vo = 0.f, t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+        float vn = 0.f;
         pair_terms(f, st.coefs, min_image(xn - st.ix[I], L0, I0), min_image(yn - st.iy[I], L1, I1),
                    min_image(zn - st.iz[I], L2, I2), vn, gx, gy, gz, lap);
-        pair_terms(f, st.coefs, min_image(xo - st.ix[I], L0, I0), min_image(yo - st.iy[I], L1, I1),
-                   min_image(zo - st.iz[I], L2, I2), vo, t0, t1, t2, t3);
+        const float vo = pair_value(f, st.coefs, min_image(xo - st.ix[I], L0, I0), min_image(yo - st.iy[I], L1, I1),
+                                    min_image(zo - st.iz[I], L2, I2));
         dv += vn - vo;
     }
     dv = wave_sum(dv);
@@ -210,38 +255,42 @@ __global__ __launch_bounds__(kJThreads) void jastrow_eval_kernel(EvalJArgs a)
     extern __shared__ unsigned char lds[];
     JStage st;
     const int N = a.j.n_elec;
-    // walker positions after the staged functors and ions
+    // walker positions, (x, y, z, 0) per electron, after the staged functors and ions
     j_stage(a.j, lds, st);
-    float* px = reinterpret_cast<float*>(st.isp + a.j.n_ion);
-    float* py = px + N;
-    float* pz = py + N;
+    float4* p = reinterpret_cast<float4*>(lds + ((reinterpret_cast<uintptr_t>(st.isp + a.j.n_ion) -
+                                                  reinterpret_cast<uintptr_t>(lds) + 15) & ~uintptr_t(15)));
     __shared__ float red[kJThreads / 64];
     const int64_t w = blockIdx.x;
     const float* Rx = a.R + w * a.wstride;
-    for (int i = threadIdx.x; i < N; i += kJThreads) {
-        px[i] = Rx[i];
-        py[i] = Rx[a.ld + i];
-        pz[i] = Rx[2 * a.ld + i];
-    }
+    for (int i = threadIdx.x; i < N; i += kJThreads) p[i] = make_float4(Rx[i], Rx[a.ld + i], Rx[2 * a.ld + i], 0.f);
     __syncthreads();
     const float L0 = a.j.L[0], L1 = a.j.L[1], L2 = a.j.L[2];
     const float I0 = a.j.Linv[0], I1 = a.j.Linv[1], I2 = a.j.Linv[2];
     const int nup = a.j.n_up;
     float jpart = 0.f;
     for (int i = threadIdx.x; i < N; i += kJThreads) {
-        const float xi = px[i], yi = py[i], zi = pz[i];
+        const float4 pi = p[i];
         const bool up = i < nup;
-        const JFun f_lo = up ? st.fun[a.j.ns] : st.fun[a.j.ns + 1];  // partners 0..nup-1
-        const JFun f_hi = up ? st.fun[a.j.ns + 1] : st.fun[a.j.ns];  // partners nup..N-1
+        const JFun fsame = st.fun[a.j.ns], fdiff = st.fun[a.j.ns + 1];
+        const JFun f_lo = up ? fsame : fdiff;  // partners 0..nup-1
+        const JFun f_hi = up ? fdiff : fsame;  // partners nup..N-1
         float v1 = 0.f, v2 = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, lap = 0.f;
-        for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            pair_terms(j < nup ? f_lo : f_hi, st.coefs, min_image(xi - px[j], L0, I0),
-                       min_image(yi - py[j], L1, I1), min_image(zi - pz[j], L2, I2), v2, gx, gy, gz, lap);
+        // The partner j = i is included: at distance 0 it adds U_same(0) to
+        // v2 (removed below) and nothing to the derivatives.
+        for (int j = 0; j < nup; ++j) {
+            const float4 pj = p[j];
+            pair_terms(f_lo, st.coefs, min_image(pi.x - pj.x, L0, I0), min_image(pi.y - pj.y, L1, I1),
+                       min_image(pi.z - pj.z, L2, I2), v2, gx, gy, gz, lap);
         }
+        for (int j = nup; j < N; ++j) {
+            const float4 pj = p[j];
+            pair_terms(f_hi, st.coefs, min_image(pi.x - pj.x, L0, I0), min_image(pi.y - pj.y, L1, I1),
+                       min_image(pi.z - pj.z, L2, I2), v2, gx, gy, gz, lap);
+        }
+        v2 -= fvalue(fsame, st.coefs, 0.f);
         for (int I = 0; I < a.j.n_ion; ++I)
-            pair_terms(st.fun[st.isp[I]], st.coefs, min_image(xi - st.ix[I], L0, I0),
-                       min_image(yi - st.iy[I], L1, I1), min_image(zi - st.iz[I], L2, I2), v1, gx, gy, gz, lap);
+            pair_terms(st.fun[st.isp[I]], st.coefs, min_image(pi.x - st.ix[I], L0, I0),
+                       min_image(pi.y - st.iy[I], L1, I1), min_image(pi.z - st.iz[I], L2, I2), v1, gx, gy, gz, lap);
         jpart += v1 + 0.5f * v2;
         float* Gw = a.G + w * 3 * (int64_t)N;
         Gw[i] = gx;
@@ -502,7 +551,7 @@ int jastrow_evaluate(const jastrow_t* j, const float* R_dev, int64_t ld, int64_t
     if (W > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "W too large");
     EvalJArgs a{j_args(j), R_dev, ld, wstride, W, J, G, L};
     void* params[] = {&a};
-    const size_t lds = stage_bytes(j) + 12 * (size_t)j->d.n_elec;
+    const size_t lds = stage_bytes(j) + 16 + 16 * (size_t)j->d.n_elec;
     QS_HIP(hipLaunchKernel((const void*)&jastrow_eval_kernel, dim3((unsigned)W), dim3(kJThreads), params, lds,
                            static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
