@@ -402,14 +402,14 @@ def main() -> int:
         del Re, Rd, jout
     jforms["system"] = "%d electrons (%d up), %d ions of 2 species, unit cube, functors with 8 intervals, rcut 0.5" % (
         NE, jd["n_up"], NI)
-    # ALU roofline: FP32 operations of the definition per pair term (58 with
-    # derivatives, 35 for a value only; DESIGN lists them) against the VALU
+    # ALU roofline: FP32 operations of the definition per pair term (66 with
+    # derivatives, 41 for a value only; DESIGN lists them) against the VALU
     # issue rate, 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (packed FP32 off).
     peak_ops = 256 * 4 * 16 * 2.4e9
     for key, v in jforms.items():
         if not isinstance(v, dict):
             continue
-        ops = 58.0 if key.startswith("evaluate") else (58.0 + 35.0) / 2
+        ops = 66.0 if key.startswith("evaluate") else (66.0 + 41.0) / 2
         v["roofline"] = {"bound": "alu", "ops_per_pair": ops, "achieved_Tops": v["pair_evals_per_s"] * ops / 1e12,
                          "peak_Tops": peak_ops / 1e12, "frac": v["pair_evals_per_s"] * ops / peak_ops}
     forms["jastrow_f32"] = jforms
