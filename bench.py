@@ -146,6 +146,7 @@ def bench_mlp(args, q, W, torch, dev, np):
         "evals_per_s_network_only": units / (ms_net * 1e-3), "evals_per_s_with_fallback": units / (ms_fb * 1e-3),
         "evals_per_s_spline_f32": units / (ms_spl * 1e-3),
         "speedup_network_only_vs_spline": ms_spl / ms_net, "speedup_with_fallback_vs_spline": ms_spl / ms_fb,
+        "dram_write_GBs_network": units * 20 / (ms_net * 1e-3) / 1e9,
         "roofline_network_kernel": {"bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
                                     "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
                                     "flop_per_position": MLP_FLOP_PER_POS},
@@ -244,6 +245,20 @@ def main() -> int:
         return [oracle.rel_err(g, r) for g, r in zip(got, ref)]
 
     e32 = eps(out32)
+    # cold variant: a 512 MB scratch write between launches evicts the caches
+    # (L2, MALL) before every timed launch
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cold = []
+    for _ in range(max(5, args.steps // 3)):
+        scratch.fill_(1)
+        ev0.record()
+        s32.eval_vgl(pos, out=out32)
+        ev1.record()
+        torch.cuda.synchronize()
+        cold.append(ev0.elapsed_time(ev1))
+    ms_cold = float(np.median(cold))
+    del scratch
     # value only (the quadrature-point evaluation): same table and positions
     ms_v, _ = time_steps(torch, lambda: s32.eval_v(pos, out=out32[0]), args.steps, args.warmup)
     vtile32 = s32.get_value_tile()
@@ -289,15 +304,27 @@ def main() -> int:
     rbuf = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
     rbuf.zero_()
     best_read = 0.0
-    for grid_r in (1024, 2048):
+    for grid_r in (1024, 2048, 4096):
         scratch = torch.empty(grid_r * 256, dtype=torch.float32, device=dev)
         ms_r, _ = time_steps(torch, lambda: q.probe_stream_read(rbuf, grid_r, out=scratch), 10, 2)
         best_read = max(best_read, rbuf.numel() / (ms_r * 1e-3) / 1e9)
     del rbuf
+    # MALL-resident read rate: the same probe over 64 MB (fits the 256 MB
+    # Infinity Cache), for tables that live there (C2)
+    mbuf = torch.ones(64 << 20, dtype=torch.uint8, device=dev)
+    mall_read = 0.0
+    for grid_r in (256, 512, 1024):
+        scratch_m = torch.empty(grid_r * 256, dtype=torch.float32, device=dev)
+        ms_m, _ = time_steps(torch, lambda: q.probe_stream_read(mbuf, grid_r, out=scratch_m), 50, 5)
+        mall_read = max(mall_read, mbuf.numel() / (ms_m * 1e-3) / 1e9)
+    del mbuf, scratch_m
     torch.cuda.empty_cache()
 
     forms = {"f32": {"evals_per_s": evals, "ms_per_step": ms32, "tile": list(tile32),
-                     "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2]},
+                     "eps_V": e32[0], "eps_G": e32[1], "eps_L": e32[2],
+                     "cold_cache": {"ms_per_launch": ms_cold, "evals_per_s": units / (ms_cold * 1e-3),
+                                    "hbm_frac": units * BYTES_PER_UNIT["f32"] / (ms_cold * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                    "note": "median of single launches, each after a 512 MB scratch write"}},
              "f32_value_only": {"evals_per_s": units / (ms_v * 1e-3), "ms_per_step": ms_v, "tile": list(vtile32),
                                 "hbm_frac": units * (64 * 4 + 4) / (ms_v * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                 "bytes_per_unit": 64 * 4 + 4},
@@ -369,6 +396,35 @@ def main() -> int:
         "bytes_per_unit": BYTES_PER_UNIT["f32"],
         "hbm_frac": units * BYTES_PER_UNIT["f32"] / (ms_vgl_hex * 1e-3) / 1e9 / PEAK_HBM_GBS}
     log("bench: vgh %.3f ms, vgh hexagonal %.3f ms, vgl hexagonal %.3f ms" % (ms_vgh, ms_vgh_hex, ms_vgl_hex))
+
+    # C2 (48^3, N = 192, FP32: a 102 MB table that the 256 MB MALL holds)
+    # against the MALL-resident read rate, and one GPU's share of an 8-way
+    # orbital split of C3 (N = 48 of 384 orbitals).
+    log("bench: C2 and the N=48 shard ...")
+    g2, N2, c2coef, _ = W.make_table(2)
+    p2 = torch.from_numpy(W.make_positions(2)).to(dev)
+    s2 = q.Spline(g2, c2coef, "f32", device=dev)
+    o2 = s2.alloc_outputs(p2.shape[0])
+    s2.autotune(p2, reps=3, out=o2)
+    ms_c2, _ = time_steps(torch, lambda: s2.eval_vgl(p2, out=o2), args.steps, args.warmup)
+    u2 = p2.shape[0] * N2
+    forms["c2_f32_mall_resident"] = {
+        "ms_per_step": ms_c2, "evals_per_s": u2 / (ms_c2 * 1e-3), "tile": list(s2.get_tile()),
+        "algorithmic_GBs": u2 * BYTES_PER_UNIT["f32"] / (ms_c2 * 1e-3) / 1e9, "mall_resident_read_GBs": mall_read,
+        "frac_of_mall_read": u2 * BYTES_PER_UNIT["f32"] / (ms_c2 * 1e-3) / 1e9 / mall_read}
+    del s2, o2, p2, c2coef
+    s48 = q.Spline(grid, np.ascontiguousarray(coefs[..., :48]), "f32", device=dev)
+    o48 = s48.alloc_outputs(B)
+    s48.autotune(pos, reps=3, out=o48)
+    ms_48, _ = time_steps(torch, lambda: s48.eval_vgl(pos, out=o48), args.steps, args.warmup)
+    u48 = B * 48
+    forms["c3_f32_shard_n48"] = {
+        "ms_per_step": ms_48, "evals_per_s": u48 / (ms_48 * 1e-3), "tile": list(s48.get_tile()),
+        "hbm_frac": u48 * BYTES_PER_UNIT["f32"] / (ms_48 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "row_bytes": int(s48.layout.row_bytes), "orbital_bytes_per_row": 48 * 4,
+        "note": "one GPU's share of C3 split 8 ways over orbitals; rows pad 192 B to 256 B"}
+    del s48, o48
+    torch.cuda.empty_cache()
 
     # Jastrow (J1 + J2, 1D cubic B-spline functors): 384 electrons, 32 ions,
     # one proposed move per walker (512 and 16384 walkers), and the full
@@ -463,12 +519,24 @@ def main() -> int:
         per_pos = (time.perf_counter() - t0) / n_cal
         want = int(args.cpu_seconds / max(per_pos, 1e-9))
         n = min(B, max(n_cal, want))
-        reps = max(1, min(20, want // B)) if want > B else 1
+        reps = max(1, min(40, want // B)) if want > B else 1
         t0 = time.perf_counter()
         for _ in range(reps):
             oracle.eval_vgl(grid, coefs, pos_np[:n], threads=ncores)
         dt = time.perf_counter() - t0
+        n1 = max(64, min(B, int(3.0 / max(per_pos * ncores, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.eval_vgl(grid, coefs, pos_np[:n1], threads=1)
+        dt1 = time.perf_counter() - t0
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": reps * n * N / dt, "unit": "orbital-VGL/s", "cores": ncores, "kind": "oracle",
+               "single_thread": {"value": n1 * N / dt1, "sample": "the first %d positions, %.1f s" % (n1, dt1)},
+               "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity": ncores},
                "sample": ("%d passes over the whole %d-position batch" % (reps, B) if n == B else
                           "the first %d of the %d positions" % (n, B)) +
                          " of the same workload, all %d orbitals; FP64 oracle (plain loops, OpenMP over "

@@ -1,20 +1,39 @@
-// Attainable-bandwidth probe: a plain streaming read of a device buffer
-// (16 bytes per lane, grid-stride), used to report the HBM rate that a
-// simple read achieves beside the published peak.
+// Attainable-bandwidth probe: a plain streaming read of a device buffer,
+// used to report the rate that a simple coalesced read achieves beside the
+// published peak.  Each workgroup reads contiguous 32 KB chunks (eight
+// 16-byte loads per lane in flight, non-temporal), chunks grid-strided.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
 
 namespace qs {
 
+constexpr int kProbeUnroll = 8;
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void stream_read_kernel(const float4* __restrict__ x, int64_t n4, float* out)
 {
-    float s = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
-        const float4 v = x[i];
-        s += v.x + v.y + v.z + v.w;
+    constexpr int64_t chunk = kProbeUnroll * 256;  // float4 per workgroup chunk
+    float s[kProbeUnroll] = {};
+    int64_t c = blockIdx.x;
+    for (; (c + 1) * chunk <= n4; c += gridDim.x) {
+        const f4* p = reinterpret_cast<const f4*>(x + c * chunk + threadIdx.x);
+        f4 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) v[u] = __builtin_nontemporal_load(p + u * 256);
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) s[u] += (v[u].x + v[u].y) + (v[u].z + v[u].w);
     }
-    out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;  // keeps the loads live
+    if (c * chunk < n4) {  // the partial last chunk, if this workgroup owns it
+        for (int64_t i = c * chunk + threadIdx.x; i < n4; i += 256) {
+            const float4 v = x[i];
+            s[0] += (v.x + v.y) + (v.z + v.w);
+        }
+    }
+    float t = 0.f;
+#pragma unroll
+    for (int u = 0; u < kProbeUnroll; ++u) t += s[u];
+    out[(int64_t)blockIdx.x * 256 + threadIdx.x] = t;  // keeps the loads live
 }
 
 }  // namespace qs
