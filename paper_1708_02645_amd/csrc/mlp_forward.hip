@@ -167,23 +167,53 @@ __global__ __launch_bounds__(64) void mlp_vgl_kernel(MlpFwdArgs a)
     const int64_t b0 = (int64_t)blockIdx.x * 16;
     const MlpOffsets o = mlp_offsets(a.nout);
 
-    // Layer-1 operands: the features of position b0 + c.
+    // Per-frequency constants, once per workgroup: the integer frequency and
+    // its Cartesian factors 2 pi k_d / cell_d and their squared norm.  They
+    // live at the start of the activation tile, which the first layer's
+    // epilogue overwrites only after the features are in registers (and
+    // after the barrier below), so the workgroup's LDS stays at one tile.
+    int32_t (*fk)[3] = reinterpret_cast<int32_t (*)[3]>(zb);
+    float (*fg)[4] = reinterpret_cast<float (*)[4]>(reinterpret_cast<unsigned char*>(zb) + kFreq * 3 * 4);
+    if (l < kFreq) {
+        float g2 = 0.f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int k = a.freqs[3 * l + d];
+            fk[l][d] = k;
+            const float gd = (float)(6.283185307179586 * k / a.cell[d]);
+            fg[l][d] = gd;
+            g2 += gd * gd;
+        }
+        fg[l][3] = g2;
+    }
+    __syncthreads();
+
+    // Layer-1 operands: the features of position b0 + c.  Phase k.u reduced
+    // modulo 1 in FP64; the hardware sine/cosine take revolutions.
     int64_t bi = b0 + c;
     if (bi >= a.B) bi = a.B - 1;  // ragged tail: computed, never stored
     double u[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = a.pos[3 * bi + d] / a.cell[d];
+    for (int d = 0; d < 3; ++d) u[d] = a.pos[3 * bi + d] * (1.0 / a.cell[d]);
     bf16x8 X1[kStreams][3];
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            float f[5];
-            feature5(a.freqs, u, a.cell, 32 * t + 8 * g + j, f);
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s) X1[s][t][j] = (__bf16)f[s];
+            const int k = 32 * t + 8 * g + j;
+            const int fi = k < kFreq ? k : k - kFreq;
+            double x = (double)fk[fi][0] * u[0] + (double)fk[fi][1] * u[1] + (double)fk[fi][2] * u[2];
+            x -= floor(x);
+            const float sn = __builtin_amdgcn_sinf((float)x), cs = __builtin_amdgcn_cosf((float)x);
+            const float val = k < kFreq ? sn : cs, dv = k < kFreq ? cs : -sn;
+            X1[0][t][j] = (__bf16)val;
+            X1[1][t][j] = (__bf16)(dv * fg[fi][0]);
+            X1[2][t][j] = (__bf16)(dv * fg[fi][1]);
+            X1[3][t][j] = (__bf16)(dv * fg[fi][2]);
+            X1[4][t][j] = (__bf16)(-fg[fi][3] * val);
         }
 
+    __syncthreads();  // every lane's features are in registers before the tile is written
     layer<3, kHidden / 64>(X1, a.Wh + o.hW1, kHidden / 16, g, c, HiddenEpi{a.P + o.b1, zb, g, c});
     __syncthreads();
     bf16x8 X[kStreams][kHidden / 32];

@@ -81,10 +81,13 @@ struct GemmArgs {
 // Launches the fused evaluation kernel (mlp_forward.hip) on a.B positions.
 int launch_mlp_forward(const MlpFwdArgs& a, hipStream_t stream);
 
-// SiLU x*s and its first two (three) derivatives, s = 1/(1 + e^-x).
+// SiLU x*s and its first two (three) derivatives, s = 1/(1 + e^-x) (the
+// hardware reciprocal, 1 ulp).
+__device__ inline float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
 __device__ inline float silu3(float x, float& d1, float& d2)
 {
-    const float s = 1.0f / (1.0f + __expf(-x));
+    const float s = sigmoid(x);
     const float oms = 1.0f - s;
     d1 = s * (1.0f + x * oms);
     d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
@@ -93,7 +96,7 @@ __device__ inline float silu3(float x, float& d1, float& d2)
 
 __device__ inline float silu4(float x, float& d1, float& d2, float& d3)
 {
-    const float s = 1.0f / (1.0f + __expf(-x));
+    const float s = sigmoid(x);
     const float oms = 1.0f - s;
     d1 = s * (1.0f + x * oms);
     d2 = s * oms * (2.0f + x * (1.0f - 2.0f * s));
