@@ -75,3 +75,41 @@ def sherman_morrison(ainv: np.ndarray, k: int, phi: np.ndarray) -> np.ndarray:
     u = t.copy()
     u[k] -= 1.0
     return a - np.outer(u, a[k]) / t[k]
+
+
+def delayed_ratio(ainv0: np.ndarray, phis, ks, k: int, q: np.ndarray) -> np.ndarray:
+    """Ratio (and, for q of several rows, the derivative sums) for moving
+    electron k while j accepted moves are pending against the stale inverse
+    ainv0 (the delayed update of the paper's outlook, built on the Woodbury
+    identity): with a_i the rows of ainv0, phis[i] the orbital vector accepted
+    for electron ks[i], S[i][l] = a_{ks[i]} . phis[l], t[i] = a_k . phis[i]
+    and y[i] = a_{ks[i]} . q, the result is a_k . q - t^T S^-1 y.  q: [n] or
+    [m, n] (one result per row).  k must not be among ks."""
+    a = np.asarray(ainv0, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    x = q @ a[k]
+    j = len(ks)
+    if j == 0:
+        return x
+    P = np.asarray(phis, dtype=np.float64).reshape(j, -1)
+    R = a[list(ks)]
+    S = R @ P.T
+    t = P @ a[k]
+    y = q @ R.T  # [..., j]
+    return x - y @ np.linalg.solve(S.T, t)
+
+
+def delayed_flush(ainv0: np.ndarray, phis, ks) -> np.ndarray:
+    """The inverse after the pending moves: ainv0 - (T - Q) S^-1 R with
+    T = ainv0 Phi (columns phis), Q = columns e_{ks}, R = rows ks of ainv0."""
+    a = np.asarray(ainv0, dtype=np.float64)
+    j = len(ks)
+    if j == 0:
+        return a.copy()
+    P = np.asarray(phis, dtype=np.float64).reshape(j, -1)
+    R = a[list(ks)]
+    T = a @ P.T
+    Q = np.zeros_like(T)
+    Q[list(ks), np.arange(j)] = 1.0
+    S = R @ P.T
+    return a - (T - Q) @ np.linalg.solve(S, R)

@@ -133,3 +133,38 @@ def test_sherman_morrison_is_the_inverse_of_the_moved_matrix(oracle):
     u[0] -= 1.0
     wrong = a0 + np.outer(u, a0[0]) / t[0]
     assert np.max(np.abs(wrong - want)) > 1e-3 * np.max(np.abs(want))
+
+
+def test_delayed_update_matches_direct_inverses(oracle):
+    """With up to 8 pending accepted moves against a stale inverse, the
+    delayed ratio and derivative sums equal those from numpy's inverse of
+    the Slater matrix with all pending moves applied, and the flush equals
+    that inverse; forgetting the correction term fails."""
+    from oracle import det
+
+    grid, n, coefs, R, Rp = _system((1.0, 1.0, 1.0), 24)
+    A0inv = np.linalg.inv(det.slater_matrix(grid, coefs, R))
+    rng = np.random.default_rng(3)
+    order = rng.permutation(n)[:9]
+    R2 = R.copy()
+    phis, ks = [], []
+    for step, k in enumerate(order):
+        rnew = rng.random(3)
+        V, G, L = oracle.eval_vgl(grid, coefs, rnew[None])
+        q = np.vstack([V[0], G[0], L[0]])  # value, gradient x/y/z, Laplacian
+        cur = np.linalg.inv(det.slater_matrix(grid, coefs, R2))
+        want = q @ cur[k]
+        got = det.delayed_ratio(A0inv, phis, ks, int(k), q)
+        scale = np.abs(q) @ np.abs(cur[k])
+        assert np.max(np.abs(got - want) / scale) < 1e-9, step
+        if ks:
+            plain = q @ A0inv[k]
+            assert np.max(np.abs(plain - want) / scale) > 1e-6  # the pending moves matter
+        if step == 8:
+            break
+        phis.append(V[0])
+        ks.append(int(k))
+        R2[k] = rnew
+    new = det.delayed_flush(A0inv, phis, ks)
+    want = np.linalg.inv(det.slater_matrix(grid, coefs, R2))
+    assert np.max(np.abs(new - want)) < 1e-8 * np.max(np.abs(want))
