@@ -189,6 +189,44 @@ int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const in
                       const int32_t* k_dev, const void* phi_dev, int64_t ld_phi, int64_t count,
                       spline_dtype dtype, void* stream);
 
+/* Delayed update of inverse Slater matrices (the Woodbury-identity scheme of
+ * the paper's outlook: several accepted moves are evaluated before A^-1 is
+ * updated, so the update becomes one rank-j product).  FP32; the inverses
+ * are n x n row-major at ainv + w*walker_stride, as for spline_det_update.
+ * Per walker the workspace keeps the pending moves: their orbital vectors
+ * phi_l, electrons k_l, and S^-1 with S[i][l] = a_{k_i} . phi_l (a_i: rows of
+ * the stale inverse).
+ *   spline_dlu_workspace_bytes / spline_dlu_create: device workspace for
+ *     `walkers` walkers, n orbitals (1..2048) and at most `delay` (1..64,
+ *     <= n) pending moves; caller-owned, 256-byte aligned; create clears it
+ *     (asynchronously on `stream`).  The handle holds host metadata only.
+ *   spline_dlu_ratio: slot s (walker walkers[s] or s, electron k[s], orbital
+ *     quantities of the proposed position V[s][n] and, optionally, G[s][3][n]
+ *     and L[s][n] as written by spline_eval_vgl) gets
+ *       a_k . q - t^T S^-1 y,  t_i = a_k . phi_i,  y_i = a_{k_i} . q,
+ *     for q = V (out[count]) or q = V, Gx, Gy, Gz, L (out[count][5]): the
+ *     determinant ratio and derivative sums against the current matrix.  k
+ *     must not be a pending electron of its walker (flush once per sweep).
+ *     A slot with k out of range gets NaN.
+ *   spline_dlu_accept: slots with k in [0, n) append their move (phi = V[s])
+ *     and border S^-1 (the Schur complement is the ratio); k = -1 marks a
+ *     rejected move.  At most `delay` accept calls between flushes
+ *     (SPL_EINVAL otherwise); a walker may appear once per call.
+ *   spline_dlu_flush: A^-1 -= (A^-1 Phi - Q) S^-1 R for every walker (R: rows
+ *     k_l of A^-1, Q: columns e_{k_l}), then no move is pending.
+ * All asynchronous on `stream`. */
+typedef struct spline_dlu_s spline_dlu_t;
+size_t spline_dlu_workspace_bytes(int32_t n, int32_t delay, int64_t walkers);
+int spline_dlu_create(int32_t n, int32_t delay, int64_t walkers, void* ws_dev, size_t ws_bytes, void* stream,
+                      spline_dlu_t** out);
+int spline_dlu_destroy(spline_dlu_t* h);
+int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv_dev, int64_t walker_stride, const int32_t* walkers_dev,
+                     const int32_t* k_dev, const float* V, const float* G, const float* L, int64_t count, float* out,
+                     void* stream);
+int spline_dlu_accept(spline_dlu_t* h, const float* ainv_dev, int64_t walker_stride, const int32_t* walkers_dev,
+                      const int32_t* k_dev, const float* V, int64_t count, void* stream);
+int spline_dlu_flush(spline_dlu_t* h, float* ainv_dev, int64_t walker_stride, void* stream);
+
 /* General (triclinic) cells.
  *
  * spline_set_lattice gives the table a general cell.  lattice: host, 9

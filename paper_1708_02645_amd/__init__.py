@@ -71,6 +71,12 @@ def lib():
             "jastrow_evaluate": ([p, p, i64, i64, i64, p, p, p, p], ctypes.c_int),
             "jastrow_dist_rows": ([p, p, i64, i64, p, p, i64, p, p, p, p, p], ctypes.c_int),
             "jastrow_accept": ([p, p, i64, i64, p, p, p, i64, p], ctypes.c_int),
+            "spline_dlu_workspace_bytes": ([i32, i32, i64], sz),
+            "spline_dlu_create": ([i32, i32, i64, p, sz, p, p], ctypes.c_int),
+            "spline_dlu_destroy": ([p], ctypes.c_int),
+            "spline_dlu_ratio": ([p, p, i64, p, p, p, p, p, i64, p, p], ctypes.c_int),
+            "spline_dlu_accept": ([p, p, i64, p, p, p, i64, p], ctypes.c_int),
+            "spline_dlu_flush": ([p, p, i64, p], ctypes.c_int),
             "spline_set_lattice": ([p, p], ctypes.c_int),
             "spline_get_lattice": ([p, p], ctypes.c_int),
             "spline_eval_vgh": ([p, p, i64, p, p, p, p], ctypes.c_int),
@@ -863,6 +869,104 @@ class Jastrow:
     def close(self):
         if getattr(self, "_h", None):
             lib().jastrow_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DelayedUpdate:
+    """Delayed (Woodbury) updates of float32 inverses ainv[W, n, n] with at
+    most `delay` pending moves per walker (include/qmcspline.h,
+    spline_dlu_*)."""
+
+    def __init__(self, n: int, delay: int, walkers: int, device="cuda", stream=None):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n, self.delay, self.walkers = int(n), int(delay), int(walkers)
+        L = lib()
+        nb = L.spline_dlu_workspace_bytes(self.n, self.delay, self.walkers)
+        if nb == 0:
+            raise SplineError(-1, "need 1 <= n <= 2048, 1 <= delay <= min(64, n), walkers >= 1")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(torch, self.device, stream)
+            check(L.spline_dlu_create(self.n, self.delay, self.walkers, ctypes.c_void_p(self.ws.data_ptr()), nb, sp,
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def _ainv(self, ainv):
+        t = self._torch
+        if not (isinstance(ainv, t.Tensor) and ainv.dtype == t.float32 and ainv.device == self.device
+                and ainv.dim() == 3 and tuple(ainv.shape[1:]) == (self.n, self.n) and ainv.is_contiguous()
+                and ainv.shape[0] >= self.walkers):
+            raise ValueError("ainv must be a contiguous float32 [>=walkers, n, n] tensor on %s" % self.device)
+        return ctypes.c_void_p(ainv.data_ptr())
+
+    def _slots(self, k, V, walkers):
+        t = self._torch
+        count = k.shape[0]
+        if not (isinstance(k, t.Tensor) and k.dtype == t.int32 and k.device == self.device and k.is_contiguous()):
+            raise ValueError("k must be a contiguous int32 tensor")
+        if not (isinstance(V, t.Tensor) and V.dtype == t.float32 and V.is_contiguous()
+                and tuple(V.shape) == (count, self.n)):
+            raise ValueError("V must be a contiguous float32 [count, n] tensor")
+        if walkers is not None:
+            if not (isinstance(walkers, t.Tensor) and walkers.dtype == t.int32 and walkers.is_contiguous()
+                    and tuple(walkers.shape) == (count,)):
+                raise ValueError("walkers must be a contiguous int32 [count] tensor")
+            if count and (int(walkers.min().item()) < 0 or int(walkers.max().item()) >= self.walkers):
+                raise ValueError("walker index out of range")
+        elif count > self.walkers:
+            raise ValueError("more slots than walkers")
+        return count
+
+    @staticmethod
+    def _p(x):
+        return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+    def ratio(self, ainv, k, V, G=None, L=None, walkers=None, out=None, stream=None):
+        t = self._torch
+        count = self._slots(k, V, walkers)
+        if (G is None) != (L is None):
+            raise ValueError("give both G and L, or neither")
+        if G is not None and (tuple(G.shape) != (count, 3, self.n) or tuple(L.shape) != (count, self.n)
+                              or not G.is_contiguous() or not L.is_contiguous()):
+            raise ValueError("G [count, 3, n] and L [count, n] must be contiguous")
+        shape = (count, 5) if G is not None else (count,)
+        out = out if out is not None else t.empty(shape, dtype=t.float32, device=self.device)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().spline_dlu_ratio(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers), self._p(k),
+                                         self._p(V), self._p(G), self._p(L), count, self._p(out), sp))
+        return out
+
+    def accept(self, ainv, k, V, walkers=None, stream=None):
+        t = self._torch
+        count = self._slots(k, V, walkers)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().spline_dlu_accept(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers), self._p(k),
+                                          self._p(V), count, sp))
+
+    def flush(self, ainv, stream=None):
+        t = self._torch
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().spline_dlu_flush(self._h, self._ainv(ainv), self.n * self.n, sp))
+        return ainv
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spline_dlu_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,451 @@
+// Delayed (Woodbury) update of inverse Slater matrices.
+//
+// Against a stale inverse A0^-1 (rows a_i), j accepted moves are kept
+// pending: the orbital vectors phi_l of the moved electrons k_l and the
+// inverse of S (S[i][l] = a_{k_i} . phi_l).  Then
+//   ratio for electron k with orbital quantities q:  a_k . q - t^T S^-1 y,
+//     t_i = a_k . phi_i,  y_i = a_{k_i} . q;
+//   accepting it borders S^-1 with the Schur complement (= the ratio);
+//   a flush applies  A0^-1 -= (A0^-1 Phi - Q) S^-1 R  (R = rows k_i of
+//   A0^-1, Q = columns e_{k_i}) once for all pending moves.
+// Per accepted move the inverse is read in j + 1 rows instead of read and
+// written whole (Sherman-Morrison); the whole matrix is read twice and
+// written once per flush.
+//
+// Workspace, per walker (floats unless noted): Phi [d][n], Sinv [d][d] (row
+// i, column l at i*d + l), M [d][n], T [n][d], K [d] int32, count int32.
+#include <algorithm>
+#include <limits>
+
+#include "common.hpp"
+
+namespace qs {
+
+constexpr int kDThreads = 256;
+constexpr int kDMaxN = 2048;
+constexpr int kDMaxDelay = 64;
+
+struct DluLayout {
+    int64_t phi, sinv, m, t, k, cnt, stride;  // offsets in 4-byte words, per-walker stride
+};
+
+static DluLayout dlu_layout(int n, int d)
+{
+    DluLayout L;
+    L.phi = 0;
+    L.sinv = L.phi + (int64_t)d * n;
+    L.m = L.sinv + (int64_t)d * d;
+    L.t = L.m + (int64_t)d * n;
+    L.k = L.t + (int64_t)n * d;
+    L.cnt = L.k + d;
+    L.stride = (L.cnt + 1 + 63) & ~int64_t(63);
+    return L;
+}
+
+struct DluArgs {
+    float* ws;
+    DluLayout L;
+    int32_t n, d;
+    float* ainv;
+    int64_t wstride;
+    const int32_t* walkers;
+    const int32_t* k;
+    const float* V;
+    const float* G;
+    const float* L_;
+    int64_t count;
+    float* out;
+};
+
+__device__ inline float dwave_sum(float x)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// The dot products of a ratio or an accept: x[q] = a . q_q, t[i] = a . phi_i,
+// y[i][q] = a_{K_i} . q_q, spread over the waves; every dot is reduced by
+// lanes in a fixed order, whichever wave takes it.
+template <int NQ>
+__device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const float* as,
+                                const float* qs, float* x, float* t, float* y)
+{
+    const int n = a.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float* Phi = st + a.L.phi;
+    const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
+    const int total = NQ + j + j * NQ;
+    for (int e = wave; e < total; e += kDThreads / 64) {
+        float s = 0.f;
+        if (e < NQ) {
+            for (int m = lane; m < n; m += 64) s = fmaf(as[m], qs[e * n + m], s);
+            s = dwave_sum(s);
+            if (lane == 0) x[e] = s;
+        } else if (e < NQ + j) {
+            const float* p = Phi + (int64_t)(e - NQ) * n;
+            for (int m = lane; m < n; m += 64) s = fmaf(as[m], p[m], s);
+            s = dwave_sum(s);
+            if (lane == 0) t[e - NQ] = s;
+        } else {
+            const int f = e - NQ - j, i = f / NQ, q = f - i * NQ;
+            const float* r = A + (int64_t)K[i] * n;
+            for (int m = lane; m < n; m += 64) s = fmaf(r[m], qs[q * n + m], s);
+            s = dwave_sum(s);
+            if (lane == 0) y[i * NQ + q] = s;
+        }
+    }
+}
+
+// Slot s -> (walker state, walker inverse, electron); false for a rejected
+// or out-of-range slot.
+__device__ inline bool dlu_slot(const DluArgs& a, int64_t s, float*& st, float*& A, int& k)
+{
+    k = a.k[s];
+    const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
+    if (k < 0 || k >= a.n || w < 0) return false;
+    st = a.ws + w * a.L.stride;
+    A = a.ainv + w * a.wstride;
+    return true;
+}
+
+template <int NQ>
+__global__ __launch_bounds__(kDThreads) void dlu_ratio_kernel(DluArgs a)
+{
+    extern __shared__ float lds[];
+    const int n = a.n, tid = threadIdx.x;
+    const int64_t s = blockIdx.x;
+    float *st, *A;
+    int k;
+    if (!dlu_slot(a, s, st, A, k)) {
+        if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
+        return;
+    }
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    float* as = lds;           // a_k [n]
+    float* qs = as + n;        // q [NQ][n]
+    float* x = qs + NQ * n;    // [NQ]
+    float* t = x + NQ;         // [d]
+    float* y = t + a.d;        // [d][NQ]
+    float* u = y + a.d * NQ;   // [d]
+    for (int m = tid; m < n; m += kDThreads) {
+        as[m] = A[(int64_t)k * n + m];
+        qs[m] = a.V[s * n + m];
+        if constexpr (NQ == 5) {
+            qs[n + m] = a.G[(3 * s) * n + m];
+            qs[2 * n + m] = a.G[(3 * s + 1) * n + m];
+            qs[3 * n + m] = a.G[(3 * s + 2) * n + m];
+            qs[4 * n + m] = a.L_[s * n + m];
+        }
+    }
+    __syncthreads();
+    dlu_dots<NQ>(a, A, st, j, as, qs, x, t, y);
+    __syncthreads();
+    const float* Sinv = st + a.L.sinv;
+    if (tid < j) {  // u = t^T S^-1
+        float v = 0.f;
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sinv[i * a.d + tid], v);
+        u[tid] = v;
+    }
+    __syncthreads();
+    if (tid < NQ) {
+        float r = x[tid];
+        for (int l = 0; l < j; ++l) r = fmaf(-u[l], y[l * NQ + tid], r);
+        a.out[s * NQ + tid] = r;
+    }
+}
+
+__global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
+{
+    extern __shared__ float lds[];
+    const int n = a.n, tid = threadIdx.x, d = a.d;
+    const int64_t s = blockIdx.x;
+    float *st, *A;
+    int k;
+    if (!dlu_slot(a, s, st, A, k)) return;
+    int32_t* cnt = reinterpret_cast<int32_t*>(st + a.L.cnt);
+    const int j = cnt[0];
+    if (j >= d) return;  // the host keeps accepts between flushes <= d
+    float* as = lds;
+    float* qs = as + n;       // v [n]
+    float* x = qs + n;        // [1]
+    float* t = x + 1;         // [d]
+    float* y = t + d;         // [d]
+    float* u = y + d;         // [d]  t^T S^-1
+    float* w = u + d;         // [d]  S^-1 y
+    float* rho = w + d;       // [1]
+    for (int m = tid; m < n; m += kDThreads) {
+        as[m] = A[(int64_t)k * n + m];
+        qs[m] = a.V[s * n + m];
+    }
+    __syncthreads();
+    dlu_dots<1>(a, A, st, j, as, qs, x, t, y);
+    __syncthreads();
+    float* Sinv = st + a.L.sinv;
+    if (tid < j) {
+        float v = 0.f;
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sinv[i * d + tid], v);
+        u[tid] = v;
+    } else if (tid >= 64 && tid < 64 + j) {
+        const int i = tid - 64;
+        float v = 0.f;
+        for (int l = 0; l < j; ++l) v = fmaf(Sinv[i * d + l], y[l], v);
+        w[i] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {  // the Schur complement: the same value as the ratio kernel's
+        float r = x[0];
+        for (int l = 0; l < j; ++l) r = fmaf(-u[l], y[l], r);
+        rho[0] = r;
+    }
+    __syncthreads();
+    const float ir = 1.f / rho[0];
+    const int j1 = j + 1;
+    for (int e = tid; e < j1 * j1; e += kDThreads) {
+        const int i = e / j1, l = e - i * j1;
+        float* p = Sinv + i * d + l;
+        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, *p);
+        else if (i < j) *p = -w[i] * ir;
+        else if (l < j) *p = -u[l] * ir;
+        else *p = ir;
+    }
+    float* Phi = st + a.L.phi + (int64_t)j * n;
+    for (int m = tid; m < n; m += kDThreads) Phi[m] = qs[m];
+    __syncthreads();
+    if (tid == 0) {
+        reinterpret_cast<int32_t*>(st + a.L.k)[j] = k;
+        cnt[0] = j + 1;
+    }
+}
+
+// Flush, step 1: M = S^-1 R (R = rows K_i of A0^-1, read before any row
+// changes).
+__global__ __launch_bounds__(kDThreads) void dlu_flush_m_kernel(DluArgs a)
+{
+    const int64_t w = blockIdx.x;
+    float* st = a.ws + w * a.L.stride;
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (j == 0) return;
+    const float* A = a.ainv + w * a.wstride;
+    const float* Sinv = st + a.L.sinv;
+    const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
+    float* M = st + a.L.m;
+    for (int m = threadIdx.x; m < a.n; m += kDThreads)
+        for (int l = 0; l < j; ++l) {
+            float v = 0.f;
+            for (int i = 0; i < j; ++i) v = fmaf(Sinv[l * a.d + i], A[(int64_t)K[i] * a.n + m], v);
+            M[(int64_t)l * a.n + m] = v;
+        }
+}
+
+// Flush, step 2: T = A0^-1 Phi^T for a block of 64 rows (LDS tiles of 64
+// columns).
+__global__ __launch_bounds__(kDThreads) void dlu_flush_t_kernel(DluArgs a)
+{
+    __shared__ float At[64][65];
+    __shared__ float Pt[kDMaxDelay][65];
+    const int64_t w = blockIdx.x;
+    float* st = a.ws + w * a.L.stride;
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (j == 0) return;
+    const int n = a.n, tid = threadIdx.x, r0 = blockIdx.y * 64;
+    const float* A = a.ainv + w * a.wstride;
+    const float* Phi = st + a.L.phi;
+    const int ri = tid & 63, lg = tid >> 6;
+    float acc[kDMaxDelay / 4];
+#pragma unroll
+    for (int c = 0; c < kDMaxDelay / 4; ++c) acc[c] = 0.f;
+    for (int m0 = 0; m0 < n; m0 += 64) {
+        for (int e = tid; e < 64 * 64; e += kDThreads) {
+            const int r = e >> 6, c = e & 63;
+            At[r][c] = (r0 + r < n && m0 + c < n) ? A[(int64_t)(r0 + r) * n + m0 + c] : 0.f;
+        }
+        for (int e = tid; e < j * 64; e += kDThreads) {
+            const int l = e >> 6, c = e & 63;
+            Pt[l][c] = m0 + c < n ? Phi[(int64_t)l * n + m0 + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kDMaxDelay / 4; ++c) {
+            const int l = lg + 4 * c;
+            if (l < j) {
+                float v = acc[c];
+                for (int mm = 0; mm < 64; ++mm) v = fmaf(At[ri][mm], Pt[l][mm], v);
+                acc[c] = v;
+            }
+        }
+        __syncthreads();
+    }
+    float* T = st + a.L.t;
+    if (r0 + ri < n) {
+#pragma unroll
+        for (int c = 0; c < kDMaxDelay / 4; ++c) {
+            const int l = lg + 4 * c;
+            if (l < j) T[(int64_t)(r0 + ri) * a.d + l] = acc[c];
+        }
+    }
+}
+
+// Flush, step 3: A0^-1 -= (T - Q) M over a 64 x 64 tile.
+__global__ __launch_bounds__(kDThreads) void dlu_flush_update_kernel(DluArgs a)
+{
+    __shared__ float Ct[64][kDMaxDelay + 1];
+    __shared__ float Mt[kDMaxDelay][65];
+    const int64_t w = blockIdx.x;
+    float* st = a.ws + w * a.L.stride;
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (j == 0) return;
+    const int n = a.n, tid = threadIdx.x, r0 = blockIdx.y * 64, c0 = blockIdx.z * 64;
+    const float* T = st + a.L.t;
+    const float* M = st + a.L.m;
+    const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
+    for (int e = tid; e < 64 * j; e += kDThreads) {
+        const int r = e / j, l = e - r * j;
+        const int i = r0 + r;
+        Ct[r][l] = i < n ? T[(int64_t)i * a.d + l] - (K[l] == i ? 1.f : 0.f) : 0.f;
+    }
+    for (int e = tid; e < j * 64; e += kDThreads) {
+        const int l = e >> 6, c = e & 63;
+        Mt[l][c] = c0 + c < n ? M[(int64_t)l * n + c0 + c] : 0.f;
+    }
+    __syncthreads();
+    const int c = tid & 63, rg = tid >> 6;
+    if (c0 + c >= n) return;
+    float* A = a.ainv + w * a.wstride;
+    for (int r = rg; r < 64 && r0 + r < n; r += 4) {
+        float v = 0.f;
+        for (int l = 0; l < j; ++l) v = fmaf(Ct[r][l], Mt[l][c], v);
+        A[(int64_t)(r0 + r) * n + c0 + c] -= v;
+    }
+}
+
+__global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < W) reinterpret_cast<int32_t*>(ws + w * L.stride + L.cnt)[0] = 0;
+}
+
+}  // namespace qs
+
+struct spline_dlu_s {
+    int32_t n, d;
+    int64_t walkers;
+    float* ws;
+    qs::DluLayout L;
+    int device;
+    int32_t accepts;  // accept calls since the last flush (upper bound of every walker's count)
+};
+
+using namespace qs;
+
+static int dlu_check(const spline_dlu_s* h, const float* ainv, int64_t wstride)
+{
+    if (!h) return fail(SPL_EINVAL, "handle is NULL");
+    if (!ainv) return fail(SPL_EINVAL, "inverse pointer is NULL");
+    if (wstride < (int64_t)h->n * h->n) return fail(SPL_EINVAL, "walker_stride must be >= n*n");
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev != h->device) return fail(SPL_EINVAL, "current HIP device differs from the workspace's device");
+    return SPL_OK;
+}
+
+extern "C" {
+
+size_t spline_dlu_workspace_bytes(int32_t n, int32_t delay, int64_t walkers)
+{
+    if (n < 1 || n > kDMaxN || delay < 1 || delay > kDMaxDelay || delay > n || walkers < 1) return 0;
+    const DluLayout L = dlu_layout(n, delay);
+    int64_t b;
+    if (!mul_ok(L.stride * 4, walkers, &b)) return 0;
+    return (size_t)b;
+}
+
+int spline_dlu_create(int32_t n, int32_t delay, int64_t walkers, void* ws_dev, size_t ws_bytes, void* stream,
+                      spline_dlu_t** out)
+{
+    if (!out) return fail(SPL_EINVAL, "out is NULL");
+    *out = nullptr;
+    const size_t need = spline_dlu_workspace_bytes(n, delay, walkers);
+    if (need == 0) return fail(SPL_EINVAL, "need 1 <= n <= 2048, 1 <= delay <= min(64, n), walkers >= 1");
+    if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) return fail(SPL_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(SPL_ENOMEM, "workspace smaller than spline_dlu_workspace_bytes()");
+    spline_dlu_s* h = new (std::nothrow) spline_dlu_s;
+    if (!h) return fail(SPL_ENOMEM, "handle allocation failed");
+    h->n = n;
+    h->d = delay;
+    h->walkers = walkers;
+    h->ws = static_cast<float*>(ws_dev);
+    h->L = dlu_layout(n, delay);
+    h->accepts = 0;
+    QS_HIP(hipGetDevice(&h->device));
+    hipLaunchKernelGGL(dlu_clear_kernel, dim3((unsigned)((walkers + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), h->ws, h->L, walkers);
+    QS_HIP(hipGetLastError());
+    *out = h;
+    return SPL_OK;
+}
+
+int spline_dlu_destroy(spline_dlu_t* h)
+{
+    delete h;
+    return SPL_OK;
+}
+
+int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv, int64_t walker_stride, const int32_t* walkers,
+                     const int32_t* k, const float* V, const float* G, const float* L, int64_t count, float* out,
+                     void* stream)
+{
+    int rc = dlu_check(h, ainv, walker_stride);
+    if (rc) return rc;
+    if (count < 0 || count > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "bad count");
+    if (count == 0) return SPL_OK;
+    if (!k || !V || !out) return fail(SPL_EINVAL, "NULL electron, value or output pointer");
+    if ((G == nullptr) != (L == nullptr)) return fail(SPL_EINVAL, "give both G and L, or neither");
+    const bool vgl = G != nullptr;
+    DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
+    void* params[] = {&a};
+    const int nq = vgl ? 5 : 1;
+    const size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 2));
+    QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_ratio_kernel<5> : (const void*)&dlu_ratio_kernel<1>,
+                           dim3((unsigned)count), dim3(kDThreads), params, lds, static_cast<hipStream_t>(stream)));
+    QS_HIP(hipGetLastError());
+    return SPL_OK;
+}
+
+int spline_dlu_accept(spline_dlu_t* h, const float* ainv, int64_t walker_stride, const int32_t* walkers,
+                      const int32_t* k, const float* V, int64_t count, void* stream)
+{
+    int rc = dlu_check(h, ainv, walker_stride);
+    if (rc) return rc;
+    if (count < 0 || count > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "bad count");
+    if (count == 0) return SPL_OK;
+    if (!k || !V) return fail(SPL_EINVAL, "NULL electron or value pointer");
+    if (h->accepts >= h->d) return fail(SPL_EINVAL, "delay reached: flush before accepting more moves");
+    DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, nullptr, nullptr,
+              count, nullptr};
+    void* params[] = {&a};
+    const size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 4 * (size_t)h->d);
+    QS_HIP(hipLaunchKernel((const void*)&dlu_accept_kernel, dim3((unsigned)count), dim3(kDThreads), params, lds,
+                           static_cast<hipStream_t>(stream)));
+    QS_HIP(hipGetLastError());
+    ++h->accepts;
+    return SPL_OK;
+}
+
+int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* stream)
+{
+    int rc = dlu_check(h, ainv, walker_stride);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DluArgs a{h->ws, h->L, h->n, h->d, ainv, walker_stride, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+    void* params[] = {&a};
+    const unsigned W = (unsigned)h->walkers, nb = (unsigned)((h->n + 63) / 64);
+    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W), dim3(kDThreads), params, 0, st));
+    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_t_kernel, dim3(W, nb), dim3(kDThreads), params, 0, st));
+    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_update_kernel, dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+    hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers);
+    QS_HIP(hipGetLastError());
+    h->accepts = 0;
+    return SPL_OK;
+}
+
+}  // extern "C"

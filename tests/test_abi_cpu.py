@@ -176,3 +176,12 @@ def test_jastrow_sizes_and_argument_checks_without_a_gpu():
                      (L.jastrow_evaluate, (None, None, 384, 3 * 384, 1, None, None, None, None)),
                      (L.jastrow_accept, (None, None, 384, 3 * 384, None, None, None, 1, None))):
         assert fn(*args) == -1 and "handle" in q.last_error()
+
+
+def test_delayed_update_sizes_without_a_gpu():
+    L = q.lib()
+    assert L.spline_dlu_workspace_bytes(384, 16, 512) % 256 == 0
+    assert L.spline_dlu_workspace_bytes(0, 16, 512) == 0
+    assert L.spline_dlu_workspace_bytes(384, 0, 512) == 0
+    assert L.spline_dlu_workspace_bytes(8, 9, 512) == 0
+    assert L.spline_dlu_ratio(None, None, 64, None, None, None, None, None, 1, None, None) == -1

@@ -1,0 +1,188 @@
+"""GPU parity of the delayed (Woodbury) determinant update (spline_dlu_*)
+against the oracle (oracle/det.py: delayed_ratio, delayed_flush).
+
+The oracle runs the same sequence of moves in FP64 with its own orbital
+values (oracle.eval_vgl at the same positions) and its own stale inverse;
+the accept/reject pattern is fixed in advance.  Error measures: a ratio or
+derivative sum against sum |a_k| |q| + sum |u_l| |y_l| (the sizes of the terms
+it is formed from); a flushed inverse against its largest entry.  Bars: 1e-4
+for one batch of pending moves on well-conditioned matrices (FP32; up to
+`delay` bordering steps, each a few roundings relative to those sizes); over
+a sweep of real Slater matrices the FP32 state drifts from the FP64 one like
+any repeated update, so there the error is held to (steps) n u cond(A), the
+drift bound used for the Sherman-Morrison sweep (u = 2^-24).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def q(torch):
+    import paper_1708_02645_amd as qq
+    qq.lib()
+    return qq
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _scale(a0, phis, ks, k, qv):
+    """sum |a_k||q| + sum_l |u_l||y_l| per row of qv (u = t^T S^-1)."""
+    a0 = np.asarray(a0)
+    base = np.abs(qv) @ np.abs(a0[k])
+    if not ks:
+        return base
+    P = np.asarray(phis).reshape(len(ks), -1)
+    R = a0[list(ks)]
+    u = np.linalg.solve((R @ P.T).T, P @ a0[k])
+    return base + np.abs(qv @ R.T) @ np.abs(u)
+
+
+def test_sweep_with_real_slater_matrices(torch, q, oracle):
+    from oracle import det
+
+    grid, n, coefs, _ = W.make_table(1)  # 16^3, 32 orbitals = electrons
+    s = q.Spline(grid, coefs, "f32")
+    Wn, delay = 4, 8
+    rng = np.random.default_rng(12)
+    R = rng.random((Wn, n, 3))
+    ainv_ref = [np.linalg.inv(det.slater_matrix(grid, coefs, R[w])) for w in range(Wn)]
+    ainv = torch.from_numpy(np.stack(ainv_ref).astype(np.float32)).cuda()
+    dl = q.DelayedUpdate(n, delay, Wn)
+    pend = [([], []) for _ in range(Wn)]  # oracle's pending (phis, ks) per walker
+    worst_r, worst_f = 0.0, 0.0
+    u32 = 2.0 ** -24
+
+    def bound(step):
+        return (step + 1) * n * u32 * max(np.linalg.cond(det.slater_matrix(grid, coefs, R[w])) for w in range(Wn))
+
+    for k in range(20):
+        if k % delay == 0 and k > 0:
+            dl.flush(ainv)
+            for w in range(Wn):
+                ainv_ref[w] = det.delayed_flush(ainv_ref[w], *pend[w])
+                pend[w] = ([], [])
+            got = ainv.cpu().numpy().astype(np.float64)
+            for w in range(Wn):
+                worst_f = max(worst_f, float(np.max(np.abs(got[w] - ainv_ref[w])) / np.max(np.abs(ainv_ref[w])))
+                              / bound(k))
+        rnew = R[:, k] + rng.normal(scale=0.03, size=(Wn, 3))
+        acc = rng.random(Wn) < 0.75
+        pos = torch.from_numpy(rnew).cuda()
+        V, G, L = s.eval_vgl(pos)
+        kd = torch.full((Wn,), k, dtype=torch.int32, device="cuda")
+        D = dl.ratio(ainv, kd, V, G, L).cpu().numpy().astype(np.float64)
+        Vr, Gr, Lr = oracle.eval_vgl(grid, coefs, rnew)
+        for w in range(Wn):
+            qv = np.vstack([Vr[w], Gr[w], Lr[w]])
+            ref = det.delayed_ratio(ainv_ref[w], pend[w][0], pend[w][1], k, qv)
+            sc = _scale(ainv_ref[w], pend[w][0], pend[w][1], k, qv)
+            worst_r = max(worst_r, float(np.max(np.abs(D[w] - ref) / sc)) / bound(k))
+        ka = torch.from_numpy(np.where(acc, k, -1).astype(np.int32)).cuda()
+        dl.accept(ainv, ka, V)
+        for w in range(Wn):
+            if acc[w]:
+                pend[w][0].append(Vr[w])
+                pend[w][1].append(k)
+                R[w, k] = rnew[w]
+    dl.flush(ainv)
+    got = ainv.cpu().numpy().astype(np.float64)
+    for w in range(Wn):
+        ainv_ref[w] = det.delayed_flush(ainv_ref[w], *pend[w])
+        worst_f = max(worst_f, float(np.max(np.abs(got[w] - ainv_ref[w])) / np.max(np.abs(ainv_ref[w])))
+                      / bound(20))
+        # the result is the inverse of the Slater matrix of the final positions
+        A = det.slater_matrix(grid, coefs, R[w])
+        assert np.max(np.abs(got[w] @ A - np.eye(n))) < 1e-3
+    _say("delayed sweep: ratio and flush error / drift bound: %.3f, %.3f" % (worst_r, worst_f))
+    assert worst_r < 1.0 and worst_f < 1.0
+
+
+@pytest.mark.parametrize("n,delay,walkers", [(384, 16, 64), (129, 5, 9), (37, 37, 3)])
+def test_synthetic_against_oracle_and_sherman_morrison(torch, q, n, delay, walkers):
+    """Well-conditioned synthetic inverses, `delay` accepted moves of distinct
+    electrons per walker, then a flush; compared with the oracle and with the
+    same moves applied one by one by spline_det_update."""
+    from oracle import det
+
+    rng = np.random.default_rng(n)
+    A = np.eye(n) + rng.normal(size=(walkers, n, n)) * (0.3 / np.sqrt(n))
+    inv0 = np.linalg.inv(A).astype(np.float32)
+    ks = np.stack([rng.permutation(n)[:delay] for _ in range(walkers)]).astype(np.int32)
+    phis = np.empty((walkers, delay, n))
+    cur = A.copy()
+    for w in range(walkers):
+        for i in range(delay):
+            phis[w, i] = cur[w][:, ks[w, i]] + rng.normal(size=n) * 0.2
+            cur[w][:, ks[w, i]] = phis[w, i]
+    phis32 = phis.astype(np.float32)
+    a_d = torch.from_numpy(inv0.copy()).cuda()
+    a_s = torch.from_numpy(inv0.copy()).cuda()
+    dl = q.DelayedUpdate(n, delay, walkers)
+    worst = 0.0
+    for i in range(delay):
+        kd = torch.from_numpy(np.ascontiguousarray(ks[:, i])).cuda()
+        Vd = torch.from_numpy(np.ascontiguousarray(phis32[:, i])).cuda()
+        r = dl.ratio(a_d, kd, Vd).cpu().numpy().astype(np.float64)
+        for w in range(0, walkers, max(1, walkers // 8)):
+            ref = det.delayed_ratio(inv0[w].astype(np.float64), phis32[w, :i].astype(np.float64), list(ks[w, :i]),
+                                    int(ks[w, i]), phis32[w, i].astype(np.float64))
+            sc = _scale(inv0[w].astype(np.float64), phis32[w, :i].astype(np.float64), list(ks[w, :i]), int(ks[w, i]),
+                        phis32[w, i][None].astype(np.float64))
+            worst = max(worst, float(np.abs(r[w] - ref) / sc[0]))
+        dl.accept(a_d, kd, Vd)
+        q.det_update(a_s, kd, Vd)
+    with pytest.raises(q.SplineError):
+        dl.accept(a_d, kd, Vd)  # delay reached
+    dl.flush(a_d)
+    got = a_d.cpu().numpy().astype(np.float64)
+    sm = a_s.cpu().numpy().astype(np.float64)
+    ferr = 0.0
+    for w in range(walkers):
+        ref = det.delayed_flush(inv0[w].astype(np.float64), phis32[w].astype(np.float64), list(ks[w]))
+        ferr = max(ferr, float(np.max(np.abs(got[w] - ref)) / np.max(np.abs(ref))))
+    smerr = float(np.max(np.abs(got - sm)) / np.max(np.abs(sm)))
+    _say("delayed n=%d d=%d: ratio %.2e flush %.2e vs SM %.2e" % (n, delay, worst, ferr, smerr))
+    assert worst <= TOL and ferr <= TOL and smerr <= 4 * TOL
+    # after the flush no move is pending: plain ratios again
+    kd = torch.from_numpy(np.ascontiguousarray(ks[:, 0])).cuda()
+    Vd = torch.from_numpy(np.ascontiguousarray(phis32[:, 0])).cuda()
+    r = dl.ratio(a_d, kd, Vd).cpu().numpy()
+    plain = np.einsum("wn,wn->w", got[np.arange(walkers), ks[:, 0]], phis32[:, 0].astype(np.float64))
+    assert np.max(np.abs(r - plain) / (np.abs(got[np.arange(walkers), ks[:, 0]]) @ np.ones(n) + 1)) < 1e-5
+
+
+def test_argument_errors(torch, q):
+    with pytest.raises(q.SplineError):
+        q.DelayedUpdate(16, 17, 2)  # delay > n
+    with pytest.raises(q.SplineError):
+        q.DelayedUpdate(4096, 8, 2)  # n too large
+    L = q.lib()
+    assert L.spline_dlu_workspace_bytes(384, 16, 512) > 0
+    assert L.spline_dlu_workspace_bytes(384, 65, 512) == 0
+    dl = q.DelayedUpdate(8, 4, 2)
+    a = torch.zeros((2, 8, 8), dtype=torch.float32, device="cuda")
+    kk = torch.tensor([99, -5], dtype=torch.int32, device="cuda")
+    V = torch.ones((2, 8), dtype=torch.float32, device="cuda")
+    r = dl.ratio(a, kk, V).cpu().numpy()
+    assert np.all(np.isnan(r))  # out-of-range electrons
+    dl.accept(a, kk, V)  # skipped, no effect
+    dl.flush(a)
+    assert float(a.abs().sum()) == 0.0
