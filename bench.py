@@ -295,6 +295,21 @@ def main() -> int:
     phi_d = torch.from_numpy(W.make_inverse_rows(3, n_w, N, seed=33) * np.float32(np.sqrt(N))).to(dev)
     ms_sm, _ = time_steps(torch, lambda: q.det_update(inv_d, k_d, phi_d), args.steps, args.warmup)
     bytes_sm = n_w * (8.0 * N * N + 4 * N + 4)
+    # Delayed update of the same inverses: 16 accepted moves per walker
+    # (value ratio against the pending moves, then accept), then one flush.
+    delay = 16
+    dl = q.DelayedUpdate(N, delay, n_w, device=dev)
+    ks_d = [((torch.arange(n_w, dtype=torch.int32, device=dev) + i) % N).to(torch.int32) for i in range(delay)]
+    r_d = torch.empty(n_w, dtype=torch.float32, device=dev)
+
+    def dlu_batch():
+        for i in range(delay):
+            dl.ratio(inv_d, ks_d[i], phi_d, out=r_d)
+            dl.accept(inv_d, ks_d[i], phi_d)
+        dl.flush(inv_d)
+
+    ms_dlu, _ = time_steps(torch, dlu_batch, max(3, args.steps // 5), 1)
+    del dl
     del s32, rows_d, Dbuf, Rbuf, rows_np, inv_d, phi_d
     torch.cuda.empty_cache()
     bpu_rvgl = 64 * 4 + 4 + 20.0 / N
@@ -336,6 +351,11 @@ def main() -> int:
              "f32_det_update": {"walkers": B // N, "n": N, "ms_per_step": ms_sm,
                                 "updates_per_s": (B // N) / (ms_sm * 1e-3), "bytes_per_update": bytes_sm / (B // N),
                                 "hbm_frac": bytes_sm / (ms_sm * 1e-3) / 1e9 / PEAK_HBM_GBS},
+             "f32_delayed_update": {"walkers": B // N, "n": N, "delay": delay, "ms_per_16_moves": ms_dlu,
+                                    "ms_per_move": ms_dlu / delay, "speedup_per_move_vs_sherman_morrison":
+                                    ms_sm / (ms_dlu / delay),
+                                    "note": "each move: ratio against the pending moves + accept; one flush per "
+                                            "16 moves (all included)"},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}

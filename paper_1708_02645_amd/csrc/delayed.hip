@@ -65,33 +65,49 @@ __device__ inline float dwave_sum(float x)
 }
 
 // The dot products of a ratio or an accept: x[q] = a . q_q, t[i] = a . phi_i,
-// y[i][q] = a_{K_i} . q_q, spread over the waves; every dot is reduced by
-// lanes in a fixed order, whichever wave takes it.
+// y[i][q] = a_{K_i} . q_q.  Each wave takes four dots at a time, so the loads
+// of all four are in flight together; every dot is accumulated over
+// m = lane, lane + 64, ... and reduced by a butterfly, the same order
+// whichever wave and slot takes it.
 template <int NQ>
 __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const float* as,
                                 const float* qs, float* x, float* t, float* y)
 {
+    constexpr int U = 4;
     const int n = a.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* Phi = st + a.L.phi;
     const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
     const int total = NQ + j + j * NQ;
-    for (int e = wave; e < total; e += kDThreads / 64) {
-        float s = 0.f;
-        if (e < NQ) {
-            for (int m = lane; m < n; m += 64) s = fmaf(as[m], qs[e * n + m], s);
-            s = dwave_sum(s);
-            if (lane == 0) x[e] = s;
-        } else if (e < NQ + j) {
-            const float* p = Phi + (int64_t)(e - NQ) * n;
-            for (int m = lane; m < n; m += 64) s = fmaf(as[m], p[m], s);
-            s = dwave_sum(s);
-            if (lane == 0) t[e - NQ] = s;
-        } else {
-            const int f = e - NQ - j, i = f / NQ, q = f - i * NQ;
-            const float* r = A + (int64_t)K[i] * n;
-            for (int m = lane; m < n; m += 64) s = fmaf(r[m], qs[q * n + m], s);
-            s = dwave_sum(s);
-            if (lane == 0) y[i * NQ + q] = s;
+    for (int e0 = wave * U; e0 < total; e0 += (kDThreads / 64) * U) {
+        const float* p1[U];
+        const float* p2[U];
+        float* dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u < total ? e0 + u : total - 1;  // a repeated last dot is computed, not stored twice
+            if (e < NQ) {
+                p1[u] = as;
+                p2[u] = qs + e * n;
+                dst[u] = x + e;
+            } else if (e < NQ + j) {
+                p1[u] = as;
+                p2[u] = Phi + (int64_t)(e - NQ) * n;
+                dst[u] = t + (e - NQ);
+            } else {
+                const int f = e - NQ - j, i = f / NQ, q = f - i * NQ;
+                p1[u] = A + (int64_t)K[i] * n;
+                p2[u] = qs + q * n;
+                dst[u] = y + i * NQ + q;
+            }
+        }
+        float s[U] = {};
+        for (int m = lane; m < n; m += 64)
+#pragma unroll
+            for (int u = 0; u < U; ++u) s[u] = fmaf(p1[u][m], p2[u][m], s[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float r = dwave_sum(s[u]);
+            if (lane == 0 && e0 + u < total) *dst[u] = r;
         }
     }
 }
@@ -218,27 +234,53 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
 }
 
 // Flush, step 1: M = S^-1 R (R = rows K_i of A0^-1, read before any row
-// changes).
+// changes).  S^-1 and K in LDS; each thread owns columns m, stages eight rows
+// of R at a time in registers and accumulates every output row.
 __global__ __launch_bounds__(kDThreads) void dlu_flush_m_kernel(DluArgs a)
 {
+    __shared__ float Ss[kDMaxDelay * kDMaxDelay];
+    __shared__ int32_t Ks[kDMaxDelay];
     const int64_t w = blockIdx.x;
     float* st = a.ws + w * a.L.stride;
     const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
     if (j == 0) return;
+    const int n = a.n, tid = threadIdx.x;
     const float* A = a.ainv + w * a.wstride;
     const float* Sinv = st + a.L.sinv;
-    const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
+    for (int e = tid; e < j * j; e += kDThreads) {
+        const int l = e / j, i = e - l * j;
+        Ss[l * kDMaxDelay + i] = Sinv[l * a.d + i];
+    }
+    if (tid < j) Ks[tid] = reinterpret_cast<const int32_t*>(st + a.L.k)[tid];
+    __syncthreads();
     float* M = st + a.L.m;
-    for (int m = threadIdx.x; m < a.n; m += kDThreads)
-        for (int l = 0; l < j; ++l) {
-            float v = 0.f;
-            for (int i = 0; i < j; ++i) v = fmaf(Sinv[l * a.d + i], A[(int64_t)K[i] * a.n + m], v);
-            M[(int64_t)l * a.n + m] = v;
+    for (int m = blockIdx.y * kDThreads + tid; m < n; m += gridDim.y * kDThreads) {
+        float acc[kDMaxDelay];
+#pragma unroll
+        for (int l = 0; l < kDMaxDelay; ++l) acc[l] = 0.f;
+        for (int i0 = 0; i0 < j; i0 += 8) {
+            float r[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r[u] = i0 + u < j ? A[(int64_t)Ks[i0 + u] * n + m] : 0.f;
+#pragma unroll
+            for (int l = 0; l < kDMaxDelay; ++l)
+                if (l < j)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (i0 + u < j) acc[l] = fmaf(Ss[l * kDMaxDelay + i0 + u], r[u], acc[l]);
         }
+#pragma unroll
+        for (int l = 0; l < kDMaxDelay; ++l)
+            if (l < j) M[(int64_t)l * n + m] = acc[l];
+    }
 }
 
-// Flush, step 2: T = A0^-1 Phi^T for a block of 64 rows (LDS tiles of 64
-// columns).
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Flush, step 2: T = A0^-1 Phi^T for a block of 64 rows, over LDS tiles of 64
+// columns; the next tile's loads (16-byte when rows allow) are in flight
+// while the current one is consumed.
+template <bool VEC>
 __global__ __launch_bounds__(kDThreads) void dlu_flush_t_kernel(DluArgs a)
 {
     __shared__ float At[64][65];
@@ -254,21 +296,44 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_t_kernel(DluArgs a)
     float acc[kDMaxDelay / 4];
 #pragma unroll
     for (int c = 0; c < kDMaxDelay / 4; ++c) acc[c] = 0.f;
-    for (int m0 = 0; m0 < n; m0 += 64) {
-        for (int e = tid; e < 64 * 64; e += kDThreads) {
-            const int r = e >> 6, c = e & 63;
-            At[r][c] = (r0 + r < n && m0 + c < n) ? A[(int64_t)(r0 + r) * n + m0 + c] : 0.f;
+    // registers for one tile: A 64 x 64 (4 x 16 values per thread), Phi j x 64 (<= 4 x 16)
+    f4v ra[4], rp[4];
+    auto fetch = [&](int m0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * kDThreads, r = e >> 4, c = (e & 15) * 4;
+            const int64_t row = r0 + r;
+            if constexpr (VEC) {
+                ra[u] = (row < n && m0 + c < n) ? *reinterpret_cast<const f4v*>(A + row * n + m0 + c)
+                                                : f4v{0.f, 0.f, 0.f, 0.f};
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ra[u][q] = (row < n && m0 + c + q < n) ? A[row * n + m0 + c + q] : 0.f;
+            }
+            const int l = r;  // Phi rows: e >> 4 < j
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rp[u][q] = (l < j && m0 + c + q < n) ? Phi[(int64_t)l * n + m0 + c + q] : 0.f;
         }
-        for (int e = tid; e < j * 64; e += kDThreads) {
-            const int l = e >> 6, c = e & 63;
-            Pt[l][c] = m0 + c < n ? Phi[(int64_t)l * n + m0 + c] : 0.f;
+    };
+    fetch(0);
+    for (int m0 = 0; m0 < n; m0 += 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * kDThreads, r = e >> 4, c = (e & 15) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                At[r][c + q] = ra[u][q];
+                if (r < j) Pt[r][c + q] = rp[u][q];
+            }
         }
         __syncthreads();
+        if (m0 + 64 < n) fetch(m0 + 64);
 #pragma unroll
         for (int c = 0; c < kDMaxDelay / 4; ++c) {
             const int l = lg + 4 * c;
             if (l < j) {
                 float v = acc[c];
+#pragma unroll 16
                 for (int mm = 0; mm < 64; ++mm) v = fmaf(At[ri][mm], Pt[l][mm], v);
                 acc[c] = v;
             }
@@ -285,11 +350,13 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_t_kernel(DluArgs a)
     }
 }
 
-// Flush, step 3: A0^-1 -= (T - Q) M over a 64 x 64 tile.
+// Flush, step 3: A0^-1 -= (T - Q) M over a 64 x 64 tile; each thread owns a
+// 4 x 4 block (rows rg + 16i, four consecutive columns), loaded before use.
+template <bool VEC>
 __global__ __launch_bounds__(kDThreads) void dlu_flush_update_kernel(DluArgs a)
 {
     __shared__ float Ct[64][kDMaxDelay + 1];
-    __shared__ float Mt[kDMaxDelay][65];
+    __shared__ __align__(16) float Mt[kDMaxDelay][64];
     const int64_t w = blockIdx.x;
     float* st = a.ws + w * a.L.stride;
     const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
@@ -298,6 +365,20 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_update_kernel(DluArgs a)
     const float* T = st + a.L.t;
     const float* M = st + a.L.m;
     const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
+    float* A = a.ainv + w * a.wstride;
+    const int cq = (tid & 15) * 4, rg = tid >> 4;
+    f4v x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t row = r0 + rg + 16 * i;
+        if constexpr (VEC) {
+            x[i] = (row < n && c0 + cq < n) ? *reinterpret_cast<const f4v*>(A + row * n + c0 + cq)
+                                            : f4v{0.f, 0.f, 0.f, 0.f};
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[i][q] = (row < n && c0 + cq + q < n) ? A[row * n + c0 + cq + q] : 0.f;
+        }
+    }
     for (int e = tid; e < 64 * j; e += kDThreads) {
         const int r = e / j, l = e - r * j;
         const int i = r0 + r;
@@ -308,13 +389,22 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_update_kernel(DluArgs a)
         Mt[l][c] = c0 + c < n ? M[(int64_t)l * n + c0 + c] : 0.f;
     }
     __syncthreads();
-    const int c = tid & 63, rg = tid >> 6;
-    if (c0 + c >= n) return;
-    float* A = a.ainv + w * a.wstride;
-    for (int r = rg; r < 64 && r0 + r < n; r += 4) {
-        float v = 0.f;
-        for (int l = 0; l < j; ++l) v = fmaf(Ct[r][l], Mt[l][c], v);
-        A[(int64_t)(r0 + r) * n + c0 + c] -= v;
+    for (int l = 0; l < j; ++l) {
+        const f4v mv = *reinterpret_cast<const f4v*>(&Mt[l][cq]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] -= Ct[rg + 16 * i][l] * mv;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t row = r0 + rg + 16 * i;
+        if (row >= n) continue;
+        if constexpr (VEC) {
+            if (c0 + cq < n) *reinterpret_cast<f4v*>(A + row * n + c0 + cq) = x[i];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c0 + cq + q < n) A[row * n + c0 + cq + q] = x[i][q];
+        }
     }
 }
 
@@ -439,9 +529,15 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
     DluArgs a{h->ws, h->L, h->n, h->d, ainv, walker_stride, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
     void* params[] = {&a};
     const unsigned W = (unsigned)h->walkers, nb = (unsigned)((h->n + 63) / 64);
-    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W), dim3(kDThreads), params, 0, st));
-    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_t_kernel, dim3(W, nb), dim3(kDThreads), params, 0, st));
-    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_update_kernel, dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+    // 16-byte row accesses when every row of every walker starts 16-byte aligned
+    const bool vec = h->n % 4 == 0 && walker_stride % 4 == 0 && (reinterpret_cast<uintptr_t>(ainv) & 15) == 0;
+    const unsigned mb = (unsigned)((h->n + kDThreads - 1) / kDThreads);
+    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W, mb), dim3(kDThreads), params, 0, st));
+    QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_t_kernel<true> : (const void*)&dlu_flush_t_kernel<false>,
+                           dim3(W, nb), dim3(kDThreads), params, 0, st));
+    QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_update_kernel<true>
+                               : (const void*)&dlu_flush_update_kernel<false>,
+                           dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
     hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers);
     QS_HIP(hipGetLastError());
     h->accepts = 0;
