@@ -309,7 +309,18 @@ def main() -> int:
         dl.flush(inv_d)
 
     ms_dlu, _ = time_steps(torch, dlu_batch, max(3, args.steps // 5), 1)
-    del dl
+    # the same batch captured once in a HIP graph and replayed (no host work per move)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dlu_batch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g_dlu = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_dlu):
+        dlu_batch()
+    ms_dlu_graph, _ = time_steps(torch, g_dlu.replay, max(3, args.steps // 5), 1)
+    del dl, g_dlu
     del s32, rows_d, Dbuf, Rbuf, rows_np, inv_d, phi_d
     torch.cuda.empty_cache()
     bpu_rvgl = 64 * 4 + 4 + 20.0 / N
@@ -354,8 +365,11 @@ def main() -> int:
              "f32_delayed_update": {"walkers": B // N, "n": N, "delay": delay, "ms_per_16_moves": ms_dlu,
                                     "ms_per_move": ms_dlu / delay, "speedup_per_move_vs_sherman_morrison":
                                     ms_sm / (ms_dlu / delay),
+                                    "ms_per_16_moves_graph": ms_dlu_graph, "ms_per_move_graph": ms_dlu_graph / delay,
+                                    "speedup_per_move_vs_sherman_morrison_graph": ms_sm / (ms_dlu_graph / delay),
                                     "note": "each move: ratio against the pending moves + accept; one flush per "
-                                            "16 moves (all included)"},
+                                            "16 moves (all included); _graph: the 16 moves and the flush replayed "
+                                            "from one HIP graph"},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}

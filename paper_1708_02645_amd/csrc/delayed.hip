@@ -24,21 +24,26 @@ namespace qs {
 constexpr int kDThreads = 256;
 constexpr int kDMaxN = 2048;
 constexpr int kDMaxDelay = 64;
+constexpr size_t kDMaxLds = 64 * 1024;  // dynamic LDS per workgroup asked for by ratio / accept
 
 struct DluLayout {
     int64_t phi, sinv, m, t, k, cnt, stride;  // offsets in 4-byte words, per-walker stride
 };
 
+// Every region starts on a 256-byte boundary (64 words), so rows of Phi and M
+// can be moved with 16-byte accesses when n is a multiple of 4.
+static int64_t dlu_pad(int64_t words) { return (words + 63) & ~int64_t(63); }
+
 static DluLayout dlu_layout(int n, int d)
 {
     DluLayout L;
     L.phi = 0;
-    L.sinv = L.phi + (int64_t)d * n;
-    L.m = L.sinv + (int64_t)d * d;
-    L.t = L.m + (int64_t)d * n;
-    L.k = L.t + (int64_t)n * d;
-    L.cnt = L.k + d;
-    L.stride = (L.cnt + 1 + 63) & ~int64_t(63);
+    L.sinv = L.phi + dlu_pad((int64_t)d * n);
+    L.m = L.sinv + dlu_pad((int64_t)d * d);
+    L.t = L.m + dlu_pad((int64_t)d * n);
+    L.k = L.t + dlu_pad((int64_t)n * d);
+    L.cnt = L.k + dlu_pad(d);
+    L.stride = L.cnt + 64;
     return L;
 }
 
@@ -55,6 +60,7 @@ struct DluArgs {
     const float* L_;
     int64_t count;
     float* out;
+    int32_t stage_sinv;  // ratio / accept: copy S^-1 to LDS first (when it fits beside the rest)
 };
 
 __device__ inline float dwave_sum(float x)
@@ -65,15 +71,16 @@ __device__ inline float dwave_sum(float x)
 }
 
 // The dot products of a ratio or an accept: x[q] = a . q_q, t[i] = a . phi_i,
-// y[i][q] = a_{K_i} . q_q.  Each wave takes four dots at a time, so the loads
-// of all four are in flight together; every dot is accumulated over
-// m = lane, lane + 64, ... and reduced by a butterfly, the same order
+// y[i][q] = a_{K_i} . q_q.  Each wave takes eight dots at a time and loads
+// four 64-column steps of all eight before using any, so a dot costs about
+// n / 256 memory round trips; every dot is accumulated over m = lane,
+// lane + 64, ... in that order and reduced by a butterfly, the same order
 // whichever wave and slot takes it.
 template <int NQ>
 __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const float* as,
                                 const float* qs, float* x, float* t, float* y)
 {
-    constexpr int U = 4;
+    constexpr int U = 8, R = 4;
     const int n = a.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* Phi = st + a.L.phi;
     const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
@@ -101,9 +108,23 @@ __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* s
             }
         }
         float s[U] = {};
-        for (int m = lane; m < n; m += 64)
+        for (int m0 = lane; m0 < n; m0 += 64 * R) {
+            float v1[U][R], v2[U][R];
 #pragma unroll
-            for (int u = 0; u < U; ++u) s[u] = fmaf(p1[u][m], p2[u][m], s[u]);
+            for (int r = 0; r < R; ++r) {
+                const int m = m0 + 64 * r;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    v1[u][r] = m < n ? p1[u][m] : 0.f;
+                    v2[u][r] = m < n ? p2[u][m] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (m0 + 64 * r < n) s[u] = fmaf(v1[u][r], v2[u][r], s[u]);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const float r = dwave_sum(s[u]);
@@ -143,6 +164,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_ratio_kernel(DluArgs a)
     float* t = x + NQ;         // [d]
     float* y = t + a.d;        // [d][NQ]
     float* u = y + a.d * NQ;   // [d]
+    float* Ss = u + a.d;       // S^-1 [j][j]
     for (int m = tid; m < n; m += kDThreads) {
         as[m] = A[(int64_t)k * n + m];
         qs[m] = a.V[s * n + m];
@@ -153,13 +175,20 @@ __global__ __launch_bounds__(kDThreads) void dlu_ratio_kernel(DluArgs a)
             qs[4 * n + m] = a.L_[s * n + m];
         }
     }
+    const float* Sinv = st + a.L.sinv;
+    if (a.stage_sinv)
+        for (int e = tid; e < j * j; e += kDThreads) {
+            const int i = e / j, l = e - i * j;
+            Ss[e] = Sinv[i * a.d + l];
+        }
+    const float* Sr = a.stage_sinv ? Ss : Sinv;
+    const int sld = a.stage_sinv ? j : a.d;
     __syncthreads();
     dlu_dots<NQ>(a, A, st, j, as, qs, x, t, y);
     __syncthreads();
-    const float* Sinv = st + a.L.sinv;
     if (tid < j) {  // u = t^T S^-1
         float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sinv[i * a.d + tid], v);
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * sld + tid], v);
         u[tid] = v;
     }
     __syncthreads();
@@ -189,22 +218,30 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
     float* u = y + d;         // [d]  t^T S^-1
     float* w = u + d;         // [d]  S^-1 y
     float* rho = w + d;       // [1]
+    float* Ss = rho + 1;      // S^-1 [j][j]
     for (int m = tid; m < n; m += kDThreads) {
         as[m] = A[(int64_t)k * n + m];
         qs[m] = a.V[s * n + m];
     }
+    float* Sinv = st + a.L.sinv;
+    if (a.stage_sinv)
+        for (int e = tid; e < j * j; e += kDThreads) {
+            const int i = e / j, l = e - i * j;
+            Ss[e] = Sinv[i * d + l];
+        }
+    const float* Sr = a.stage_sinv ? Ss : Sinv;
+    const int sld = a.stage_sinv ? j : d;
     __syncthreads();
     dlu_dots<1>(a, A, st, j, as, qs, x, t, y);
     __syncthreads();
-    float* Sinv = st + a.L.sinv;
     if (tid < j) {
         float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sinv[i * d + tid], v);
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * sld + tid], v);
         u[tid] = v;
     } else if (tid >= 64 && tid < 64 + j) {
         const int i = tid - 64;
         float v = 0.f;
-        for (int l = 0; l < j; ++l) v = fmaf(Sinv[i * d + l], y[l], v);
+        for (int l = 0; l < j; ++l) v = fmaf(Sr[i * sld + l], y[l], v);
         w[i] = v;
     }
     __syncthreads();
@@ -219,7 +256,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
     for (int e = tid; e < j1 * j1; e += kDThreads) {
         const int i = e / j1, l = e - i * j1;
         float* p = Sinv + i * d + l;
-        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, *p);
+        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, Sr[i * sld + l]);
         else if (i < j) *p = -w[i] * ir;
         else if (l < j) *p = -u[l] * ir;
         else *p = ir;
@@ -408,6 +445,133 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_update_kernel(DluArgs a)
     }
 }
 
+// Flush, steps 2 and 3 in one pass for n <= 512 (n a multiple of 4) and at
+// most 16 pending moves: a workgroup holds 32 rows of A0^-1 in registers
+// (thread: 4 rows x 4*NC columns, columns cg*4 + 128c), forms their rows of
+// T = A0^-1 Phi^T, then C = T - Q and A0^-1 -= C M, and writes the rows back:
+// A0^-1 is read once and written once.  Phi, then M, are staged through one
+// LDS buffer; C goes through LDS as well.
+//
+// The 32 threads of a row group sum their four row partials by halving: the
+// two lanes 16 apart exchange two rows each, lanes 8 apart one row, then the
+// eight lanes that share a row reduce it (cross-lane moves within a 16-lane
+// row), so every dot costs 1.5 exchanges instead of 5.
+constexpr int kFuseMaxJ = 16;
+constexpr int kFuseMaxN = 512;
+constexpr int kFuseRows = 32;
+
+template <int CTRL>
+__device__ inline float dpp_f(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// p[0..3]: this lane's partials of rows 0..3 of its row group (32 lanes).
+// Returns the full sum of row 2*bit4 + bit3 of the lane id, the same in all
+// eight lanes holding that row.
+__device__ inline float row_group_sum(const float p[4], int lane)
+{
+    const bool h16 = lane & 16, h8 = lane & 8;
+    const float k0 = h16 ? p[2] : p[0], k1 = h16 ? p[3] : p[1];
+    const float s0 = h16 ? p[0] : p[2], s1 = h16 ? p[1] : p[3];
+    const float r0 = k0 + __shfl_xor(s0, 16, 64);
+    const float r1 = k1 + __shfl_xor(s1, 16, 64);
+    float v = (h8 ? r1 : r0) + dpp_f<0x128>(h8 ? r0 : r1);  // row_ror:8 = lane xor 8 within 16
+    v += dpp_f<0xB1>(v);                                     // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);                                     // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);                                    // row_half_mirror
+    return v;
+}
+
+// FULL: n == 128 NC and n a multiple of 32, so no row or column of a block
+// needs a bounds check.
+template <int NC, bool FULL>
+__global__ __launch_bounds__(kDThreads) void dlu_flush_fused_kernel(DluArgs a)
+{
+    constexpr int kStage = kFuseMaxJ * kFuseMaxN / 4 / kDThreads;  // 16-byte loads per thread for Phi or M
+    __shared__ __align__(16) float P[kFuseMaxJ * kFuseMaxN];
+    __shared__ __align__(16) float Cs[kFuseMaxJ][kFuseRows];
+    __shared__ int32_t Ks[kFuseMaxJ];
+    const int64_t w = blockIdx.x;
+    const float* st = a.ws + w * a.L.stride;
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (j == 0 || j > kFuseMaxJ) return;  // the host takes this path only with <= 16 accepts since the last flush
+    const int n = a.n, tid = threadIdx.x, cg = tid & 31, lane = tid & 63;
+    const int rl = (tid >> 5) * 4, rb0 = blockIdx.y * kFuseRows, row0 = rb0 + rl;
+    float* A = a.ainv + w * a.wstride;
+    auto inside = [&](int i, int c) { return FULL || (row0 + i < n && cg * 4 + 128 * c < n); };
+    // every global load of the block is issued here: 4 x NC row chunks, Phi and M
+    f4v x[4][NC];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            x[i][c] = inside(i, c) ? *reinterpret_cast<const f4v*>(A + (int64_t)(row0 + i) * n + cg * 4 + 128 * c)
+                                   : f4v{0.f, 0.f, 0.f, 0.f};
+    const int nv = j * n / 4;
+    const f4v* phi = reinterpret_cast<const f4v*>(st + a.L.phi);
+    const f4v* mrows = reinterpret_cast<const f4v*>(st + a.L.m);
+    f4v sp[kStage], sm[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+        const int e = tid + u * kDThreads;
+        sp[u] = e < nv ? phi[e] : f4v{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+        const int e = tid + u * kDThreads;
+        sm[u] = e < nv ? mrows[e] : f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    f4v* P4 = reinterpret_cast<f4v*>(P);
+#pragma unroll
+    for (int u = 0; u < kStage; ++u)
+        if (tid + u * kDThreads < nv) P4[tid + u * kDThreads] = sp[u];
+    if (tid < j) Ks[tid] = reinterpret_cast<const int32_t*>(st + a.L.k)[tid];
+    __syncthreads();
+    const int mine = rl + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);  // row (in the block) this lane's sums belong to
+    for (int l = 0; l < j; ++l) {
+        float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (inside(0, c)) {  // columns past n hold zeros in x; skip their LDS reads
+                const f4v ph = P4[(l * n + cg * 4 + 128 * c) >> 2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    p[i] = fmaf(x[i][c].x, ph.x, p[i]);
+                    p[i] = fmaf(x[i][c].y, ph.y, p[i]);
+                    p[i] = fmaf(x[i][c].z, ph.z, p[i]);
+                    p[i] = fmaf(x[i][c].w, ph.w, p[i]);
+                }
+            }
+        }
+        const float t = row_group_sum(p, lane);
+        if ((lane & 7) == 0) Cs[l][mine] = t - (Ks[l] == rb0 + mine ? 1.f : 0.f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kStage; ++u)
+        if (tid + u * kDThreads < nv) P4[tid + u * kDThreads] = sm[u];
+    __syncthreads();
+    for (int l = 0; l < j; ++l) {
+        const f4v cv = *reinterpret_cast<const f4v*>(&Cs[l][rl]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (inside(0, c)) {
+                const f4v mv = P4[(l * n + cg * 4 + 128 * c) >> 2];
+                x[0][c] -= cv.x * mv;
+                x[1][c] -= cv.y * mv;
+                x[2][c] -= cv.z * mv;
+                x[3][c] -= cv.w * mv;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (inside(i, c)) *reinterpret_cast<f4v*>(A + (int64_t)(row0 + i) * n + cg * 4 + 128 * c) = x[i][c];
+}
+
 __global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W)
 {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,7 +658,9 @@ int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv, int64_t walker_st
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
     void* params[] = {&a};
     const int nq = vgl ? 5 : 1;
-    const size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 2));
+    size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 2));
+    a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
+    if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
     QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_ratio_kernel<5> : (const void*)&dlu_ratio_kernel<1>,
                            dim3((unsigned)count), dim3(kDThreads), params, lds, static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
@@ -513,7 +679,9 @@ int spline_dlu_accept(spline_dlu_t* h, const float* ainv, int64_t walker_stride,
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, nullptr, nullptr,
               count, nullptr};
     void* params[] = {&a};
-    const size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 4 * (size_t)h->d);
+    size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 4 * (size_t)h->d);
+    a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
+    if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
     QS_HIP(hipLaunchKernel((const void*)&dlu_accept_kernel, dim3((unsigned)count), dim3(kDThreads), params, lds,
                            static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
@@ -533,11 +701,23 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
     const bool vec = h->n % 4 == 0 && walker_stride % 4 == 0 && (reinterpret_cast<uintptr_t>(ainv) & 15) == 0;
     const unsigned mb = (unsigned)((h->n + kDThreads - 1) / kDThreads);
     QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W, mb), dim3(kDThreads), params, 0, st));
-    QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_t_kernel<true> : (const void*)&dlu_flush_t_kernel<false>,
-                           dim3(W, nb), dim3(kDThreads), params, 0, st));
-    QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_update_kernel<true>
-                               : (const void*)&dlu_flush_update_kernel<false>,
-                           dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+    if (vec && h->n <= kFuseMaxN && h->accepts <= kFuseMaxJ) {
+        static const void* const fused[2][4] = {
+            {(const void*)&dlu_flush_fused_kernel<1, false>, (const void*)&dlu_flush_fused_kernel<2, false>,
+             (const void*)&dlu_flush_fused_kernel<3, false>, (const void*)&dlu_flush_fused_kernel<4, false>},
+            {(const void*)&dlu_flush_fused_kernel<1, true>, (const void*)&dlu_flush_fused_kernel<2, true>,
+             (const void*)&dlu_flush_fused_kernel<3, true>, (const void*)&dlu_flush_fused_kernel<4, true>}};
+        const int nc = (h->n + 127) / 128;
+        const bool full = h->n == 128 * nc;  // then also a multiple of 32
+        const unsigned rb = (unsigned)((h->n + kFuseRows - 1) / kFuseRows);
+        QS_HIP(hipLaunchKernel(fused[full][nc - 1], dim3(W, rb), dim3(kDThreads), params, 0, st));
+    } else {
+        QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_t_kernel<true> : (const void*)&dlu_flush_t_kernel<false>,
+                               dim3(W, nb), dim3(kDThreads), params, 0, st));
+        QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_update_kernel<true>
+                                   : (const void*)&dlu_flush_update_kernel<false>,
+                               dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+    }
     hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers);
     QS_HIP(hipGetLastError());
     h->accepts = 0;

@@ -115,7 +115,12 @@ def test_sweep_with_real_slater_matrices(torch, q, oracle):
     assert worst_r < 1.0 and worst_f < 1.0
 
 
-@pytest.mark.parametrize("n,delay,walkers", [(384, 16, 64), (129, 5, 9), (37, 37, 3)])
+# flush paths: one pass for n % 4 == 0, n <= 512 and <= 16 pending moves
+# (384: 3 column chunks; 260: ragged column chunk and row block; 512 and 64:
+# 4 and 1 chunks); separate T and update passes otherwise (129, 37: n not a
+# multiple of 4; 200 with 20 pending moves)
+@pytest.mark.parametrize("n,delay,walkers", [(384, 16, 64), (260, 16, 5), (512, 16, 3), (64, 12, 7), (129, 5, 9),
+                                             (37, 37, 3), (200, 20, 4)])
 def test_synthetic_against_oracle_and_sherman_morrison(torch, q, n, delay, walkers):
     """Well-conditioned synthetic inverses, `delay` accepted moves of distinct
     electrons per walker, then a flush; compared with the oracle and with the

@@ -93,3 +93,59 @@ def test_pbyp_step_in_a_graph(torch, q):
         got = [t.cpu().numpy() for t in (D, J, ainv_g, R_g)]
         for a, b in zip(got, ref):
             np.testing.assert_array_equal(a, b)
+
+
+def test_delayed_batch_in_a_graph(torch, q):
+    """Four moves through the delayed update (ratio with derivatives against
+    the pending moves, accept of a subset of walkers) and the flush, captured
+    once and replayed: every replay equals the eager sequence bit for bit.
+    The flush clears the pending moves, so each replay starts from none."""
+    grid, N, coefs, _ = W.make_table(1)  # 16^3, 32 orbitals
+    s = q.Spline(grid, coefs, "f32")
+    Wn, moves = 64, 4
+    rng = np.random.default_rng(9)
+    inv0 = np.linalg.inv(np.eye(N) + 0.3 * rng.normal(size=(Wn, N, N)) / np.sqrt(N)).astype(np.float32)
+    dev = torch.device("cuda")
+    pos = [torch.from_numpy(rng.random((Wn, 3))).to(dev) for _ in range(moves)]
+    kk = [torch.full((Wn,), 3 * i + 1, dtype=torch.int32, device=dev) for i in range(moves)]
+    ka = [torch.from_numpy(np.where(rng.random(Wn) < 0.7, 3 * i + 1, -1).astype(np.int32)).to(dev)
+          for i in range(moves)]
+    vgl = [s.eval_vgl(p) for p in pos]
+    D = [torch.empty((Wn, 5), dtype=torch.float32, device=dev) for _ in range(moves)]
+
+    def batch(dl, ainv):
+        for i in range(moves):
+            V, G, L = vgl[i]
+            dl.ratio(ainv, kk[i], V, G, L, out=D[i])
+            dl.accept(ainv, ka[i], V)
+        dl.flush(ainv)
+
+    dl_e = q.DelayedUpdate(N, moves, Wn)
+    a_e = torch.from_numpy(inv0.copy()).to(dev)
+    batch(dl_e, a_e)
+    torch.cuda.synchronize()
+    ref = [d.cpu().numpy().copy() for d in D] + [a_e.cpu().numpy()]
+    assert all(np.isfinite(r).all() for r in ref)
+
+    dl_g = q.DelayedUpdate(N, moves, Wn)
+    a_g = torch.from_numpy(inv0.copy()).to(dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch(dl_g, a_g)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch(dl_g, a_g)
+    for rep in range(3):
+        a_g.copy_(torch.from_numpy(inv0).to(dev))
+        for d in D:
+            d.zero_()
+        torch.cuda.synchronize()
+        _ = s.eval_vgl(pos[0])  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = [d.cpu().numpy() for d in D] + [a_g.cpu().numpy()]
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
