@@ -572,6 +572,150 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_fused_kernel(DluArgs a)
             if (inside(i, c)) *reinterpret_cast<f4v*>(A + (int64_t)(row0 + i) * n + cg * 4 + 128 * c) = x[i][c];
 }
 
+// Flush, steps 2 and 3 on FP32 matrix cores, for n a multiple of 16 up to
+// 384 and at most 16 pending moves (zero-padded to 16).  A workgroup owns a
+// walker, Phi and M sit in LDS ([16][n + 4]), and each wave streams blocks of
+// 16 rows of A0^-1 (block b + 4 loaded while block b is worked on).  A block
+// lives in registers in the accumulator layout of the transposed product:
+// for column tile t (16 columns) lane (g = lane/16, c = lane%16) holds row c,
+// columns 16t + 4g .. 16t + 4g + 3, one 16-byte load.  The same registers
+// are the A operand of T = A0^-1 Phi^T when the 4-wide k-steps are taken as
+// columns {16t + 4g + r}: step (t, r) multiplies register r of tile t with
+// Phi[c][16t + 4g + r].  T (rows 4g + r, column c) goes through LDS to become
+// the B operand -C^T of the update  A0^-1^T += M^T (-C^T), accumulated onto
+// the block's registers, which are then stored.
+constexpr int kMfmaMaxN = 384;
+
+__device__ inline f4v mfma16x16x4(float a, float b, f4v c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// LDS row strides (words): Phi rows at 4 mod 64 (the 16-byte reads of a
+// quarter wave, one per row, fall in distinct banks), M rows at 16 mod 64
+// (the four row groups of a wave's 4-byte reads are 16 banks apart).
+__host__ __device__ inline int dlu_mfma_ldp(int n) { return n + ((4 - n) & 63); }
+__host__ __device__ inline int dlu_mfma_ldm(int n) { return n + ((16 - n) & 63); }
+
+// EXACT: n == 16 NT, so no tile needs a guard; the guards of the other
+// builds are branches, after which the compiler waits for every load in
+// flight, the prefetch included.
+template <int NT, bool EXACT>
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 2 : 4))) void dlu_flush_mfma_kernel(DluArgs a)
+{
+    extern __shared__ __align__(16) float lds[];
+    const int64_t w = blockIdx.x;
+    const float* st = a.ws + w * a.L.stride;
+    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (j == 0 || j > kFuseMaxJ) return;  // the host takes this path only with <= 16 accepts since the last flush
+    const int n = EXACT ? 16 * NT : a.n, nt = EXACT ? NT : n >> 4, tid = threadIdx.x, lane = tid & 63,
+              wave = tid >> 6;
+    const int ldp = dlu_mfma_ldp(n), ldm = dlu_mfma_ldm(n);
+    const int g = lane >> 4, c = lane & 15;
+    float* Ph = lds;                                   // Phi [16][ldp]
+    float* Ms = Ph + 16 * ldp;                         // M [16][ldm]
+    float* Cw = Ms + 16 * ldm + wave * (16 * 20);      // -C of this wave's block [16][20]
+    int32_t* Ks = reinterpret_cast<int32_t*>(Ms + 16 * ldm + 4 * 16 * 20);
+    float* Ss = Ms + 16 * ldm;  // S^-1 [16][17], zero-padded, in wave 0's C scratch (not in use yet)
+    const int n4 = n >> 2;
+    float* A = a.ainv + w * a.wstride;
+    if (tid < 16) Ks[tid] = tid < j ? reinterpret_cast<const int32_t*>(st + a.L.k)[tid] : -1;
+    {
+        const int l = tid >> 4, i = tid & 15;
+        Ss[l * 17 + i] = (l < j && i < j) ? st[a.L.sinv + l * a.d + i] : 0.f;
+    }
+    __syncthreads();
+    // Phi, and R = rows K of A0^-1 (read before any row of this walker
+    // changes: every row of it is updated by this workgroup, after the
+    // barriers below) into the M buffer
+    const f4v* phi = reinterpret_cast<const f4v*>(st + a.L.phi);
+    for (int e = tid; e < 16 * n4; e += kDThreads) {
+        const int l = e / n4, q = e - l * n4;
+        const f4v z = {0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f4v*>(Ph + l * ldp + 4 * q) = l < j ? phi[e] : z;
+        *reinterpret_cast<f4v*>(Ms + l * ldm + 4 * q) =
+            l < j ? *reinterpret_cast<const f4v*>(A + (int64_t)Ks[l] * n + 4 * q) : z;
+    }
+    __syncthreads();
+    // M = S^-1 R in place: a thread owns whole columns
+    for (int m = tid; m < n; m += kDThreads) {
+        float r[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = Ms[i * ldm + m];
+#pragma unroll
+        for (int l = 0; l < 16; ++l) {
+            float v = 0.f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v = fmaf(Ss[l * 17 + i], r[i], v);
+            Ms[l * ldm + m] = v;
+        }
+    }
+    __syncthreads();
+    auto load = [&](int b, f4v* X) {
+        const float* src = A + (int64_t)(16 * b + c) * n + 4 * g;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t < nt) X[t] = *reinterpret_cast<const f4v*>(src + 16 * t);
+    };
+    // one block, held in X: T, -C through LDS, the update, the stores
+    auto block = [&](int b, f4v* X) {
+        f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t < nt) {
+                const f4v ph = *reinterpret_cast<const f4v*>(Ph + c * ldp + 16 * t + 4 * g);
+                acc0 = mfma16x16x4(X[t].x, ph.x, acc0);
+                acc1 = mfma16x16x4(X[t].y, ph.y, acc1);
+                acc0 = mfma16x16x4(X[t].z, ph.z, acc0);
+                acc1 = mfma16x16x4(X[t].w, ph.w, acc1);
+            }
+        }
+        const f4v T = acc0 + acc1;  // T[16b + 4g + r][c]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 4 * g + r;
+            Cw[row * 20 + c] = (Ks[c] == 16 * b + row ? 1.f : 0.f) - T[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float cb[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) cb[s4] = Cw[c * 20 + 4 * s4 + g];  // -C[row c][4 s4 + g]
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                if (t < nt) X[t] = mfma16x16x4(Ms[(4 * s4 + g) * ldm + 16 * t + c], cb[s4], X[t]);
+        float* dst = A + (int64_t)(16 * b + c) * n + 4 * g;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t < nt) *reinterpret_cast<f4v*>(dst + 16 * t) = X[t];
+    };
+    // Blocks wave, wave + 4, ...; X and Y swap roles every block.  The loads
+    // of the next block are issued unconditionally (the last one repeats a
+    // block of this wave, an L2 hit): a conditional load would end in a
+    // branch, after which the compiler waits for all loads in flight.
+    const int nblk = (nt - wave + 3) >> 2;
+    if (nblk <= 0) return;
+    auto blk = [&](int i) { return wave + 4 * min(i, nblk - 1); };
+    f4v X[NT], Y[NT];
+    load(blk(0), X);
+#pragma unroll 1
+    for (int i = 0;; i += 2) {
+        load(blk(i + 1), Y);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the work it overlaps
+        block(blk(i), X);
+        if (i + 1 >= nblk) break;
+        load(blk(i + 2), X);
+        __builtin_amdgcn_sched_barrier(0);
+        block(blk(i + 1), Y);
+        if (i + 2 >= nblk) break;
+    }
+}
+
+static size_t dlu_mfma_lds(int n) { return sizeof(float) * (16 * (size_t)(dlu_mfma_ldp(n) + dlu_mfma_ldm(n)) + 4 * 16 * 20) + 16 * 4; }
+
 __global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W)
 {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -700,23 +844,40 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
     // 16-byte row accesses when every row of every walker starts 16-byte aligned
     const bool vec = h->n % 4 == 0 && walker_stride % 4 == 0 && (reinterpret_cast<uintptr_t>(ainv) & 15) == 0;
     const unsigned mb = (unsigned)((h->n + kDThreads - 1) / kDThreads);
-    QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W, mb), dim3(kDThreads), params, 0, st));
-    if (vec && h->n <= kFuseMaxN && h->accepts <= kFuseMaxJ) {
-        static const void* const fused[2][4] = {
-            {(const void*)&dlu_flush_fused_kernel<1, false>, (const void*)&dlu_flush_fused_kernel<2, false>,
-             (const void*)&dlu_flush_fused_kernel<3, false>, (const void*)&dlu_flush_fused_kernel<4, false>},
-            {(const void*)&dlu_flush_fused_kernel<1, true>, (const void*)&dlu_flush_fused_kernel<2, true>,
-             (const void*)&dlu_flush_fused_kernel<3, true>, (const void*)&dlu_flush_fused_kernel<4, true>}};
-        const int nc = (h->n + 127) / 128;
-        const bool full = h->n == 128 * nc;  // then also a multiple of 32
-        const unsigned rb = (unsigned)((h->n + kFuseRows - 1) / kFuseRows);
-        QS_HIP(hipLaunchKernel(fused[full][nc - 1], dim3(W, rb), dim3(kDThreads), params, 0, st));
+    // matrix-core pass (M formed inside): n a multiple of 16 in [16, 64] or
+    // (128, 384], the register tiles compiled (64 < n <= 128 would spill)
+    const int nt = h->n / 16;
+    const bool mfma = vec && h->n % 16 == 0 && h->n <= kMfmaMaxN && (nt <= 4 || nt > 8) && h->accepts <= kFuseMaxJ;
+    if (mfma) {
+        static const void* const mk[2][6] = {
+            {(const void*)&dlu_flush_mfma_kernel<4, false>, nullptr, (const void*)&dlu_flush_mfma_kernel<12, false>,
+             (const void*)&dlu_flush_mfma_kernel<16, false>, (const void*)&dlu_flush_mfma_kernel<20, false>,
+             (const void*)&dlu_flush_mfma_kernel<24, false>},
+            {(const void*)&dlu_flush_mfma_kernel<4, true>, nullptr, (const void*)&dlu_flush_mfma_kernel<12, true>,
+             (const void*)&dlu_flush_mfma_kernel<16, true>, (const void*)&dlu_flush_mfma_kernel<20, true>,
+             (const void*)&dlu_flush_mfma_kernel<24, true>}};
+        const int ti = (nt + 3) / 4 - 1;
+        QS_HIP(hipLaunchKernel(mk[nt == 4 * (ti + 1)][ti], dim3(W), dim3(kDThreads), params, dlu_mfma_lds(h->n), st));
     } else {
-        QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_t_kernel<true> : (const void*)&dlu_flush_t_kernel<false>,
-                               dim3(W, nb), dim3(kDThreads), params, 0, st));
-        QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_update_kernel<true>
-                                   : (const void*)&dlu_flush_update_kernel<false>,
-                               dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+        QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W, mb), dim3(kDThreads), params, 0, st));
+        if (vec && h->n <= kFuseMaxN && h->accepts <= kFuseMaxJ) {
+            static const void* const fused[2][4] = {
+                {(const void*)&dlu_flush_fused_kernel<1, false>, (const void*)&dlu_flush_fused_kernel<2, false>,
+                 (const void*)&dlu_flush_fused_kernel<3, false>, (const void*)&dlu_flush_fused_kernel<4, false>},
+                {(const void*)&dlu_flush_fused_kernel<1, true>, (const void*)&dlu_flush_fused_kernel<2, true>,
+                 (const void*)&dlu_flush_fused_kernel<3, true>, (const void*)&dlu_flush_fused_kernel<4, true>}};
+            const int nc = (h->n + 127) / 128;
+            const bool full = h->n == 128 * nc;  // then also a multiple of 32
+            const unsigned rb = (unsigned)((h->n + kFuseRows - 1) / kFuseRows);
+            QS_HIP(hipLaunchKernel(fused[full][nc - 1], dim3(W, rb), dim3(kDThreads), params, 0, st));
+        } else {
+            QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_t_kernel<true>
+                                       : (const void*)&dlu_flush_t_kernel<false>,
+                                   dim3(W, nb), dim3(kDThreads), params, 0, st));
+            QS_HIP(hipLaunchKernel(vec ? (const void*)&dlu_flush_update_kernel<true>
+                                       : (const void*)&dlu_flush_update_kernel<false>,
+                                   dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
+        }
     }
     hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers);
     QS_HIP(hipGetLastError());
