@@ -572,10 +572,10 @@ __global__ __launch_bounds__(kDThreads) void dlu_flush_fused_kernel(DluArgs a)
             if (inside(i, c)) *reinterpret_cast<f4v*>(A + (int64_t)(row0 + i) * n + cg * 4 + 128 * c) = x[i][c];
 }
 
-// Flush, steps 2 and 3 on FP32 matrix cores, for n a multiple of 16 up to
-// 384 and at most 16 pending moves (zero-padded to 16).  A workgroup owns a
-// walker, Phi and M sit in LDS ([16][n + 4]), and each wave streams blocks of
-// 16 rows of A0^-1 (block b + 4 loaded while block b is worked on).  A block
+// The whole flush on FP32 matrix cores, for n a multiple of 16 up to 384 and
+// at most 16 pending moves (zero-padded to 16).  A workgroup owns a walker:
+// it stages Phi and R (rows K of A0^-1) in LDS, forms M = S^-1 R in place,
+// and each wave then takes blocks of 16 rows of A0^-1.  A block
 // lives in registers in the accumulator layout of the transposed product:
 // for column tile t (16 columns) lane (g = lane/16, c = lane%16) holds row c,
 // columns 16t + 4g .. 16t + 4g + 3, one 16-byte load.  The same registers
@@ -600,9 +600,10 @@ __host__ __device__ inline int dlu_mfma_ldm(int n) { return n + ((16 - n) & 63);
 // EXACT: n == 16 NT, so no tile needs a guard; the guards of the other
 // builds are branches, after which the compiler waits for every load in
 // flight, the prefetch included.
-template <int NT, bool EXACT>
-__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 2 : 4))) void dlu_flush_mfma_kernel(DluArgs a)
+template <int NT, bool EXACT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void dlu_flush_mfma_kernel(DluArgs a)
 {
+    constexpr int kThreads = 64 * NW;
     extern __shared__ __align__(16) float lds[];
     const int64_t w = blockIdx.x;
     const float* st = a.ws + w * a.L.stride;
@@ -615,12 +616,12 @@ __global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 
     float* Ph = lds;                                   // Phi [16][ldp]
     float* Ms = Ph + 16 * ldp;                         // M [16][ldm]
     float* Cw = Ms + 16 * ldm + wave * (16 * 20);      // -C of this wave's block [16][20]
-    int32_t* Ks = reinterpret_cast<int32_t*>(Ms + 16 * ldm + 4 * 16 * 20);
+    int32_t* Ks = reinterpret_cast<int32_t*>(Ms + 16 * ldm + NW * 16 * 20);
     float* Ss = Ms + 16 * ldm;  // S^-1 [16][17], zero-padded, in wave 0's C scratch (not in use yet)
     const int n4 = n >> 2;
     float* A = a.ainv + w * a.wstride;
     if (tid < 16) Ks[tid] = tid < j ? reinterpret_cast<const int32_t*>(st + a.L.k)[tid] : -1;
-    {
+    if (tid < 256) {
         const int l = tid >> 4, i = tid & 15;
         Ss[l * 17 + i] = (l < j && i < j) ? st[a.L.sinv + l * a.d + i] : 0.f;
     }
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 
     // changes: every row of it is updated by this workgroup, after the
     // barriers below) into the M buffer
     const f4v* phi = reinterpret_cast<const f4v*>(st + a.L.phi);
-    for (int e = tid; e < 16 * n4; e += kDThreads) {
+    for (int e = tid; e < 16 * n4; e += kThreads) {
         const int l = e / n4, q = e - l * n4;
         const f4v z = {0.f, 0.f, 0.f, 0.f};
         *reinterpret_cast<f4v*>(Ph + l * ldp + 4 * q) = l < j ? phi[e] : z;
@@ -638,7 +639,7 @@ __global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 
     }
     __syncthreads();
     // M = S^-1 R in place: a thread owns whole columns
-    for (int m = tid; m < n; m += kDThreads) {
+    for (int m = tid; m < n; m += kThreads) {
         float r[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) r[i] = Ms[i * ldm + m];
@@ -692,29 +693,25 @@ __global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(NT > 
         for (int t = 0; t < NT; ++t)
             if (t < nt) *reinterpret_cast<f4v*>(dst + 16 * t) = X[t];
     };
-    // Blocks wave, wave + 4, ...; X and Y swap roles every block.  The loads
-    // of the next block are issued unconditionally (the last one repeats a
-    // block of this wave, an L2 hit): a conditional load would end in a
-    // branch, after which the compiler waits for all loads in flight.
-    const int nblk = (nt - wave + 3) >> 2;
-    if (nblk <= 0) return;
-    auto blk = [&](int i) { return wave + 4 * min(i, nblk - 1); };
-    f4v X[NT], Y[NT];
-    load(blk(0), X);
+    // Blocks wave, wave + NW, ...; each wave loads a block, works on it and
+    // stores it, and the eight waves of the workgroup (up to 16 per CU) hide
+    // each other's loads.  (Holding a second block for a prefetch doubles
+    // the registers and halves the waves; measured slower.)
+    const int nblk = (nt - wave + NW - 1) / NW;
+    f4v X[NT];
 #pragma unroll 1
-    for (int i = 0;; i += 2) {
-        load(blk(i + 1), Y);
-        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the work it overlaps
-        block(blk(i), X);
-        if (i + 1 >= nblk) break;
-        load(blk(i + 2), X);
-        __builtin_amdgcn_sched_barrier(0);
-        block(blk(i + 1), Y);
-        if (i + 2 >= nblk) break;
+    for (int i = 0; i < nblk; ++i) {
+        const int b = wave + NW * i;
+        load(b, X);
+        block(b, X);
     }
 }
 
-static size_t dlu_mfma_lds(int n) { return sizeof(float) * (16 * (size_t)(dlu_mfma_ldp(n) + dlu_mfma_ldm(n)) + 4 * 16 * 20) + 16 * 4; }
+constexpr int kMfmaWaves = 8;  // waves per workgroup of the matrix-core flush
+static size_t dlu_mfma_lds(int n)
+{
+    return sizeof(float) * (16 * (size_t)(dlu_mfma_ldp(n) + dlu_mfma_ldm(n)) + kMfmaWaves * 16 * 20) + 16 * 4;
+}
 
 __global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W)
 {
@@ -844,20 +841,24 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
     // 16-byte row accesses when every row of every walker starts 16-byte aligned
     const bool vec = h->n % 4 == 0 && walker_stride % 4 == 0 && (reinterpret_cast<uintptr_t>(ainv) & 15) == 0;
     const unsigned mb = (unsigned)((h->n + kDThreads - 1) / kDThreads);
-    // matrix-core pass (M formed inside): n a multiple of 16 in [16, 64] or
-    // (128, 384], the register tiles compiled (64 < n <= 128 would spill)
+    // matrix-core pass (M formed inside): n a multiple of 16 up to 384
     const int nt = h->n / 16;
-    const bool mfma = vec && h->n % 16 == 0 && h->n <= kMfmaMaxN && (nt <= 4 || nt > 8) && h->accepts <= kFuseMaxJ;
+    const bool mfma = vec && h->n % 16 == 0 && h->n <= kMfmaMaxN && h->accepts <= kFuseMaxJ;
     if (mfma) {
-        static const void* const mk[2][6] = {
-            {(const void*)&dlu_flush_mfma_kernel<4, false>, nullptr, (const void*)&dlu_flush_mfma_kernel<12, false>,
-             (const void*)&dlu_flush_mfma_kernel<16, false>, (const void*)&dlu_flush_mfma_kernel<20, false>,
-             (const void*)&dlu_flush_mfma_kernel<24, false>},
-            {(const void*)&dlu_flush_mfma_kernel<4, true>, nullptr, (const void*)&dlu_flush_mfma_kernel<12, true>,
-             (const void*)&dlu_flush_mfma_kernel<16, true>, (const void*)&dlu_flush_mfma_kernel<20, true>,
-             (const void*)&dlu_flush_mfma_kernel<24, true>}};
+        constexpr int V = kMfmaWaves;
+        // exact builds for n = 64, 128, ..., 384; otherwise the next larger
+        // guarded build (a guarded 8-tile build spills)
+        static const void* const exact[6] = {
+            (const void*)&dlu_flush_mfma_kernel<4, true, V>,  (const void*)&dlu_flush_mfma_kernel<8, true, V>,
+            (const void*)&dlu_flush_mfma_kernel<12, true, V>, (const void*)&dlu_flush_mfma_kernel<16, true, V>,
+            (const void*)&dlu_flush_mfma_kernel<20, true, V>, (const void*)&dlu_flush_mfma_kernel<24, true, V>};
+        static const void* const guarded[6] = {
+            (const void*)&dlu_flush_mfma_kernel<4, false, V>,  (const void*)&dlu_flush_mfma_kernel<12, false, V>,
+            (const void*)&dlu_flush_mfma_kernel<12, false, V>, (const void*)&dlu_flush_mfma_kernel<16, false, V>,
+            (const void*)&dlu_flush_mfma_kernel<20, false, V>, (const void*)&dlu_flush_mfma_kernel<24, false, V>};
         const int ti = (nt + 3) / 4 - 1;
-        QS_HIP(hipLaunchKernel(mk[nt == 4 * (ti + 1)][ti], dim3(W), dim3(kDThreads), params, dlu_mfma_lds(h->n), st));
+        const void* fn = nt == 4 * (ti + 1) ? exact[ti] : guarded[ti];
+        QS_HIP(hipLaunchKernel(fn, dim3(W), dim3(64 * V), params, dlu_mfma_lds(h->n), st));
     } else {
         QS_HIP(hipLaunchKernel((const void*)&dlu_flush_m_kernel, dim3(W, mb), dim3(kDThreads), params, 0, st));
         if (vec && h->n <= kFuseMaxN && h->accepts <= kFuseMaxJ) {

@@ -116,12 +116,13 @@ def test_sweep_with_real_slater_matrices(torch, q, oracle):
 
 
 # flush paths, all with <= 16 pending moves unless noted: matrix cores for n
-# a multiple of 16 in [16, 64] or (128, 384] (384: 24 column tiles, 144: 9 of
-# a 12-tile build, 64 with 12 moves); one vector pass for other n % 4 == 0 up
-# to 512 (260: ragged column chunk and row block; 512; 96); separate T and
-# update passes otherwise (129, 37: n not a multiple of 4; 200 with 20 moves)
-@pytest.mark.parametrize("n,delay,walkers", [(384, 16, 64), (144, 16, 6), (64, 12, 7), (260, 16, 5), (512, 16, 3),
-                                             (96, 8, 5), (129, 5, 9), (37, 37, 3), (200, 20, 4)])
+# a multiple of 16 up to 384 (384 and 128: exact 24- and 8-tile builds; 64
+# with 12 moves; 144 and 96: 9 and 6 tiles of a guarded 12-tile build); one
+# vector pass for other n % 4 == 0 up to 512 (260: ragged column chunk and
+# row block; 512); separate T and update passes otherwise (129, 37: n not a
+# multiple of 4; 200 with 20 moves)
+@pytest.mark.parametrize("n,delay,walkers", [(384, 16, 64), (128, 16, 4), (64, 12, 7), (144, 16, 6), (96, 8, 5),
+                                             (260, 16, 5), (512, 16, 3), (129, 5, 9), (37, 37, 3), (200, 20, 4)])
 def test_synthetic_against_oracle_and_sherman_morrison(torch, q, n, delay, walkers):
     """Well-conditioned synthetic inverses, `delay` accepted moves of distinct
     electrons per walker, then a flush; compared with the oracle and with the
