@@ -77,13 +77,12 @@ __device__ inline float dwave_sum(float x)
 // lane + 64, ... in that order and reduced by a butterfly, the same order
 // whichever wave and slot takes it.
 template <int NQ>
-__device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const float* as,
-                                const float* qs, float* x, float* t, float* y)
+__device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const int32_t* K,
+                                const float* as, const float* qs, float* x, float* t, float* y)
 {
     constexpr int U = 8, R = 4;
     const int n = a.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* Phi = st + a.L.phi;
-    const int32_t* K = reinterpret_cast<const int32_t*>(st + a.L.k);
     const int total = NQ + j + j * NQ;
     for (int e0 = wave * U; e0 < total; e0 += (kDThreads / 64) * U) {
         const float* p1[U];
@@ -133,15 +132,55 @@ __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* s
     }
 }
 
-// Slot s -> (walker state, walker inverse, electron); false for a rejected
-// or out-of-range slot.
-__device__ inline bool dlu_slot(const DluArgs& a, int64_t s, float*& st, float*& A, int& k)
+// rows[r][m] = src[r][m] for r < NR, m < n: every load of a thread is issued
+// before any of its LDS stores (up to four columns per row at a time).
+template <int NR>
+__device__ inline void dlu_copy_rows(float* rows, const float* const (&src)[NR], int n)
 {
+    for (int m0 = threadIdx.x; m0 < n; m0 += 4 * kDThreads) {
+        float v[NR][4];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[r][u] = m0 + u * kDThreads < n ? src[r][m0 + u * kDThreads] : 0.f;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (m0 + u * kDThreads < n) rows[r * n + m0 + u * kDThreads] = v[r][u];
+    }
+}
+
+// The staging shared by ratio and accept, in two rounds of memory traffic:
+// first the slot and the orbital quantities of the proposed position (they
+// depend on the slot alone), then, for a valid slot, the pending count, the
+// electrons K, S^-1 (whole d x d block, when staged) and row k of A0^-1.
+// Returns false for a rejected or out-of-range slot (k outside [0, n) or a
+// negative walker).
+template <int NQ>
+__device__ inline bool dlu_stage(const DluArgs& a, int64_t s, float* as, float* qs, int32_t* Ks, float* Ss,
+                                 float*& st, float*& A, int& k, int& j)
+{
+    const int n = a.n, tid = threadIdx.x;
     k = a.k[s];
     const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
-    if (k < 0 || k >= a.n || w < 0) return false;
+    if constexpr (NQ == 5) {
+        const float* const src[5] = {a.V + s * n, a.G + (3 * s) * n, a.G + (3 * s + 1) * n, a.G + (3 * s + 2) * n,
+                                     a.L_ + s * n};
+        dlu_copy_rows<5>(qs, src, n);
+    } else {
+        const float* const src[1] = {a.V + s * n};
+        dlu_copy_rows<1>(qs, src, n);
+    }
+    if (k < 0 || k >= n || w < 0) return false;
     st = a.ws + w * a.L.stride;
     A = a.ainv + w * a.wstride;
+    j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
+    if (tid < a.d) Ks[tid] = reinterpret_cast<const int32_t*>(st + a.L.k)[tid];
+    if (a.stage_sinv)
+        for (int e = tid; e < a.d * a.d; e += kDThreads) Ss[e] = st[a.L.sinv + e];
+    const float* const row[1] = {A + (int64_t)k * n};
+    dlu_copy_rows<1>(as, row, n);
     return true;
 }
 
@@ -149,46 +188,29 @@ template <int NQ>
 __global__ __launch_bounds__(kDThreads) void dlu_ratio_kernel(DluArgs a)
 {
     extern __shared__ float lds[];
-    const int n = a.n, tid = threadIdx.x;
+    const int n = a.n, tid = threadIdx.x, d = a.d;
     const int64_t s = blockIdx.x;
+    float* as = lds;                                   // a_k [n]
+    float* qs = as + n;                                // q [NQ][n]
+    float* x = qs + NQ * n;                            // [NQ]
+    float* t = x + NQ;                                 // [d]
+    float* y = t + d;                                  // [d][NQ]
+    float* u = y + d * NQ;                             // [d]
+    int32_t* Ks = reinterpret_cast<int32_t*>(u + d);   // [d]
+    float* Ss = reinterpret_cast<float*>(Ks + d);      // S^-1 [d][d] when staged
     float *st, *A;
-    int k;
-    if (!dlu_slot(a, s, st, A, k)) {
+    int k, j;
+    if (!dlu_stage<NQ>(a, s, as, qs, Ks, Ss, st, A, k, j)) {
         if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
         return;
     }
-    const int j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
-    float* as = lds;           // a_k [n]
-    float* qs = as + n;        // q [NQ][n]
-    float* x = qs + NQ * n;    // [NQ]
-    float* t = x + NQ;         // [d]
-    float* y = t + a.d;        // [d][NQ]
-    float* u = y + a.d * NQ;   // [d]
-    float* Ss = u + a.d;       // S^-1 [j][j]
-    for (int m = tid; m < n; m += kDThreads) {
-        as[m] = A[(int64_t)k * n + m];
-        qs[m] = a.V[s * n + m];
-        if constexpr (NQ == 5) {
-            qs[n + m] = a.G[(3 * s) * n + m];
-            qs[2 * n + m] = a.G[(3 * s + 1) * n + m];
-            qs[3 * n + m] = a.G[(3 * s + 2) * n + m];
-            qs[4 * n + m] = a.L_[s * n + m];
-        }
-    }
-    const float* Sinv = st + a.L.sinv;
-    if (a.stage_sinv)
-        for (int e = tid; e < j * j; e += kDThreads) {
-            const int i = e / j, l = e - i * j;
-            Ss[e] = Sinv[i * a.d + l];
-        }
-    const float* Sr = a.stage_sinv ? Ss : Sinv;
-    const int sld = a.stage_sinv ? j : a.d;
+    const float* Sr = a.stage_sinv ? Ss : st + a.L.sinv;  // row stride d either way
     __syncthreads();
-    dlu_dots<NQ>(a, A, st, j, as, qs, x, t, y);
+    dlu_dots<NQ>(a, A, st, j, Ks, as, qs, x, t, y);
     __syncthreads();
     if (tid < j) {  // u = t^T S^-1
         float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * sld + tid], v);
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * d + tid], v);
         u[tid] = v;
     }
     __syncthreads();
@@ -204,44 +226,33 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
     extern __shared__ float lds[];
     const int n = a.n, tid = threadIdx.x, d = a.d;
     const int64_t s = blockIdx.x;
-    float *st, *A;
-    int k;
-    if (!dlu_slot(a, s, st, A, k)) return;
-    int32_t* cnt = reinterpret_cast<int32_t*>(st + a.L.cnt);
-    const int j = cnt[0];
-    if (j >= d) return;  // the host keeps accepts between flushes <= d
     float* as = lds;
-    float* qs = as + n;       // v [n]
-    float* x = qs + n;        // [1]
-    float* t = x + 1;         // [d]
-    float* y = t + d;         // [d]
-    float* u = y + d;         // [d]  t^T S^-1
-    float* w = u + d;         // [d]  S^-1 y
-    float* rho = w + d;       // [1]
-    float* Ss = rho + 1;      // S^-1 [j][j]
-    for (int m = tid; m < n; m += kDThreads) {
-        as[m] = A[(int64_t)k * n + m];
-        qs[m] = a.V[s * n + m];
-    }
+    float* qs = as + n;                                // v [n]
+    float* x = qs + n;                                 // [1]
+    float* t = x + 1;                                  // [d]
+    float* y = t + d;                                  // [d]
+    float* u = y + d;                                  // [d]  t^T S^-1
+    float* w = u + d;                                  // [d]  S^-1 y
+    float* rho = w + d;                                // [1]
+    int32_t* Ks = reinterpret_cast<int32_t*>(rho + 1);  // [d]
+    float* Ss = reinterpret_cast<float*>(Ks + d);      // S^-1 [d][d] when staged
+    float *st, *A;
+    int k, j;
+    if (!dlu_stage<1>(a, s, as, qs, Ks, Ss, st, A, k, j)) return;
+    if (j >= d) return;  // the host keeps accepts between flushes <= d
     float* Sinv = st + a.L.sinv;
-    if (a.stage_sinv)
-        for (int e = tid; e < j * j; e += kDThreads) {
-            const int i = e / j, l = e - i * j;
-            Ss[e] = Sinv[i * d + l];
-        }
-    const float* Sr = a.stage_sinv ? Ss : Sinv;
-    const int sld = a.stage_sinv ? j : d;
+    const float* Sr = a.stage_sinv ? Ss : Sinv;  // row stride d either way
     __syncthreads();
-    dlu_dots<1>(a, A, st, j, as, qs, x, t, y);
+    dlu_dots<1>(a, A, st, j, Ks, as, qs, x, t, y);
     __syncthreads();
     if (tid < j) {
         float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * sld + tid], v);
+        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * d + tid], v);
         u[tid] = v;
     } else if (tid >= 64 && tid < 64 + j) {
         const int i = tid - 64;
         float v = 0.f;
-        for (int l = 0; l < j; ++l) v = fmaf(Sr[i * sld + l], y[l], v);
+        for (int l = 0; l < j; ++l) v = fmaf(Sr[i * d + l], y[l], v);
         w[i] = v;
     }
     __syncthreads();
@@ -256,7 +267,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
     for (int e = tid; e < j1 * j1; e += kDThreads) {
         const int i = e / j1, l = e - i * j1;
         float* p = Sinv + i * d + l;
-        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, Sr[i * sld + l]);
+        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, Sr[i * d + l]);
         else if (i < j) *p = -w[i] * ir;
         else if (l < j) *p = -u[l] * ir;
         else *p = ir;
@@ -266,7 +277,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
     __syncthreads();
     if (tid == 0) {
         reinterpret_cast<int32_t*>(st + a.L.k)[j] = k;
-        cnt[0] = j + 1;
+        reinterpret_cast<int32_t*>(st + a.L.cnt)[0] = j + 1;
     }
 }
 
@@ -799,7 +810,7 @@ int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv, int64_t walker_st
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
     void* params[] = {&a};
     const int nq = vgl ? 5 : 1;
-    size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 2));
+    size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 3));
     a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
     if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
     QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_ratio_kernel<5> : (const void*)&dlu_ratio_kernel<1>,
@@ -820,7 +831,7 @@ int spline_dlu_accept(spline_dlu_t* h, const float* ainv, int64_t walker_stride,
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, nullptr, nullptr,
               count, nullptr};
     void* params[] = {&a};
-    size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 4 * (size_t)h->d);
+    size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 5 * (size_t)h->d);
     a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
     if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
     QS_HIP(hipLaunchKernel((const void*)&dlu_accept_kernel, dim3((unsigned)count), dim3(kDThreads), params, lds,
