@@ -182,7 +182,9 @@ int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, con
  *               fitting in 64 KB of LDS (n <= 8190 FP32, 4094 FP64)
  *   walker_stride >= n*n; ld_phi >= n; pointers element-aligned
  * A slot with k outside [0, n) or a negative walker index leaves its walker
- * untouched.  Listing one walker twice in a call races; rho == 0 (a move that
+ * untouched; other walker indices must address inverses inside the caller's
+ * buffer (the library does not know its extent).  Listing one walker twice in
+ * a call races; rho == 0 (a move that
  * must not be accepted) gives non-finite entries.  Asynchronous on `stream`;
  * count == 0 is a no-op.  SPL_EINVAL on bad sizes or pointers. */
 int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const int32_t* walkers_dev,
@@ -202,18 +204,20 @@ int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const in
  *     (asynchronously on `stream`).  The handle holds host metadata only.
  *   spline_dlu_ratio: slot s (walker walkers[s] or s, electron k[s], orbital
  *     quantities of the proposed position V[s][n] and, optionally, G[s][3][n]
- *     and L[s][n] as written by spline_eval_vgl) gets
+ *     and L[s][n] as written by spline_eval_vgl; with walkers == NULL,
+ *     count <= walkers of the workspace, else SPL_EINVAL) gets
  *       a_k . q - t^T S^-1 y,  t_i = a_k . phi_i,  y_i = a_{k_i} . q,
  *     for q = V (out[count]) or q = V, Gx, Gy, Gz, L (out[count][5]): the
  *     determinant ratio and derivative sums against the current matrix.  k
  *     must not be a pending electron of its walker (flush once per sweep).
- *     A slot with k out of range gets NaN.
+ *     A slot with k or its walker out of range gets NaN.
  *   spline_dlu_accept: slots with k in [0, n) append their move (phi = V[s])
  *     and border S^-1 (the Schur complement is the ratio); k = -1 marks a
- *     rejected move.  At most `delay` accept calls between flushes
+ *     rejected move, and a slot whose walker is out of range is skipped.  At most `delay` accept calls between flushes
  *     (SPL_EINVAL otherwise); a walker may appear once per call.
  *   spline_dlu_flush: A^-1 -= (A^-1 Phi - Q) S^-1 R for every walker (R: rows
- *     k_l of A^-1, Q: columns e_{k_l}), then no move is pending.
+ *     k_l of A^-1, Q: columns e_{k_l}), then no move is pending.  ainv must
+ *     hold the inverses of all `walkers` walkers of the workspace.
  * All asynchronous on `stream`. */
 typedef struct spline_dlu_s spline_dlu_t;
 size_t spline_dlu_workspace_bytes(int32_t n, int32_t delay, int64_t walkers);

@@ -923,8 +923,7 @@ class DelayedUpdate:
             if not (isinstance(walkers, t.Tensor) and walkers.dtype == t.int32 and walkers.is_contiguous()
                     and tuple(walkers.shape) == (count,)):
                 raise ValueError("walkers must be a contiguous int32 [count] tensor")
-            if count and (int(walkers.min().item()) < 0 or int(walkers.max().item()) >= self.walkers):
-                raise ValueError("walker index out of range")
+            # indices are range-checked by the kernels (NaN ratio, skipped accept): no host sync here
         elif count > self.walkers:
             raise ValueError("more slots than walkers")
         return count

@@ -61,6 +61,7 @@ struct DluArgs {
     int64_t count;
     float* out;
     int32_t stage_sinv;  // ratio / accept: copy S^-1 to LDS first (when it fits beside the rest)
+    int64_t nwalkers;    // walkers of the workspace: a slot's walker must be in [0, nwalkers)
 };
 
 __device__ inline float dwave_sum(float x)
@@ -156,7 +157,7 @@ __device__ inline void dlu_copy_rows(float* rows, const float* const (&src)[NR],
 // depend on the slot alone), then, for a valid slot, the pending count, the
 // electrons K, S^-1 (whole d x d block, when staged) and row k of A0^-1.
 // Returns false for a rejected or out-of-range slot (k outside [0, n) or a
-// negative walker).
+// walker outside [0, walkers)).
 template <int NQ>
 __device__ inline bool dlu_stage(const DluArgs& a, int64_t s, float* as, float* qs, int32_t* Ks, float* Ss,
                                  float*& st, float*& A, int& k, int& j)
@@ -172,7 +173,7 @@ __device__ inline bool dlu_stage(const DluArgs& a, int64_t s, float* as, float* 
         const float* const src[1] = {a.V + s * n};
         dlu_copy_rows<1>(qs, src, n);
     }
-    if (k < 0 || k >= n || w < 0) return false;
+    if (k < 0 || k >= n || w < 0 || w >= a.nwalkers) return false;
     st = a.ws + w * a.L.stride;
     A = a.ainv + w * a.wstride;
     j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
@@ -806,8 +807,10 @@ int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv, int64_t walker_st
     if (count == 0) return SPL_OK;
     if (!k || !V || !out) return fail(SPL_EINVAL, "NULL electron, value or output pointer");
     if ((G == nullptr) != (L == nullptr)) return fail(SPL_EINVAL, "give both G and L, or neither");
+    if (!walkers && count > h->walkers) return fail(SPL_EINVAL, "count exceeds the workspace's walkers");
     const bool vgl = G != nullptr;
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
+    a.nwalkers = h->walkers;
     void* params[] = {&a};
     const int nq = vgl ? 5 : 1;
     size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 3));
@@ -828,8 +831,10 @@ int spline_dlu_accept(spline_dlu_t* h, const float* ainv, int64_t walker_stride,
     if (count == 0) return SPL_OK;
     if (!k || !V) return fail(SPL_EINVAL, "NULL electron or value pointer");
     if (h->accepts >= h->d) return fail(SPL_EINVAL, "delay reached: flush before accepting more moves");
+    if (!walkers && count > h->walkers) return fail(SPL_EINVAL, "count exceeds the workspace's walkers");
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, nullptr, nullptr,
               count, nullptr};
+    a.nwalkers = h->walkers;
     void* params[] = {&a};
     size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 5 * (size_t)h->d);
     a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
@@ -847,6 +852,7 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     DluArgs a{h->ws, h->L, h->n, h->d, ainv, walker_stride, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+    a.nwalkers = h->walkers;
     void* params[] = {&a};
     const unsigned W = (unsigned)h->walkers, nb = (unsigned)((h->n + 63) / 64);
     // 16-byte row accesses when every row of every walker starts 16-byte aligned

@@ -193,3 +193,22 @@ def test_argument_errors(torch, q):
     dl.accept(a, kk, V)  # skipped, no effect
     dl.flush(a)
     assert float(a.abs().sum()) == 0.0
+    # walker indices outside the workspace: NaN ratio, accept skipped
+    wl = torch.tensor([5, -1], dtype=torch.int32, device="cuda")
+    k2 = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    r = dl.ratio(a, k2, V, walkers=wl).cpu().numpy()
+    assert np.all(np.isnan(r))
+    dl.accept(a, k2, V, walkers=wl)
+    dl.flush(a)
+    assert float(a.abs().sum()) == 0.0
+    # with no walker list, more slots than walkers is refused by the library itself
+    import ctypes  # the binding's own check fires first, so call the C ABI directly
+    k3 = torch.zeros(3, dtype=torch.int32, device="cuda")
+    V3 = torch.ones((3, 8), dtype=torch.float32, device="cuda")
+    o3 = torch.empty(3, dtype=torch.float32, device="cuda")
+    rc = L.spline_dlu_ratio(dl._h, ctypes.c_void_p(a.data_ptr()), 64, None, ctypes.c_void_p(k3.data_ptr()),
+                            ctypes.c_void_p(V3.data_ptr()), None, None, 3, ctypes.c_void_p(o3.data_ptr()), None)
+    assert rc == -1
+    rc = L.spline_dlu_accept(dl._h, ctypes.c_void_p(a.data_ptr()), 64, None, ctypes.c_void_p(k3.data_ptr()),
+                             ctypes.c_void_p(V3.data_ptr()), 3, None)
+    assert rc == -1
