@@ -33,7 +33,9 @@
  *
  * Electron positions: R_dev float; coordinate a (0 = x, 1 = y, 2 = z) of
  * electron i of walker w is R_dev[w*wstride + a*ld + i], ld >= n_elec,
- * wstride >= 3*ld.
+ * wstride >= 3*ld.  A walker list (walkers[s]) must address walkers inside
+ * the caller's buffer (the library does not know its extent); a negative
+ * index gives NaN outputs for its slot, or is skipped by jastrow_accept.
  */
 #ifndef QMCJASTROW_H
 #define QMCJASTROW_H

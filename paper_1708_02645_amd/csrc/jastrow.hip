@@ -192,11 +192,11 @@ __global__ __launch_bounds__(kJThreads) void jastrow_move_kernel(MoveArgs a)
     if (s >= a.count) return;
     const int k = a.k[s];
     float* o = a.out + 5 * s;
-    if (k < 0 || k >= a.j.n_elec) {
+    const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
+    if (k < 0 || k >= a.j.n_elec || w < 0) {
         if (lane < 5) o[lane] = __builtin_nanf("");
         return;
     }
-    const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
     const float* Rx = a.R + w * a.wstride;
     const float* Ry = Rx + a.ld;
     const float* Rz = Ry + a.ld;
@@ -328,10 +328,18 @@ __global__ __launch_bounds__(kJThreads) void jastrow_rows_kernel(RowArgs a)
     const int64_t s = (int64_t)blockIdx.x * (kJThreads / 64) + (threadIdx.x >> 6);
     if (s >= a.count) return;
     const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
-    const float* Rx = a.R + w * a.wstride;
+    const float* Rx = a.R + (w < 0 ? 0 : w) * a.wstride;
     const float x = (float)a.r[3 * s], y = (float)a.r[3 * s + 1], z = (float)a.r[3 * s + 2];
     const int N = a.j.n_elec, NI = a.j.n_ion;
-    for (int i = lane; i < N; i += 64) {
+    if (w < 0) {  // no such walker: its electron rows are NaN
+        for (int i = lane; i < N; i += 64) {
+            a.de[s * N + i] = __builtin_nanf("");
+            a.dre[(3 * s) * N + i] = __builtin_nanf("");
+            a.dre[(3 * s + 1) * N + i] = __builtin_nanf("");
+            a.dre[(3 * s + 2) * N + i] = __builtin_nanf("");
+        }
+    }
+    for (int i = lane; i < N && w >= 0; i += 64) {
         const float dx = min_image(Rx[i] - x, a.j.L[0], a.j.Linv[0]);
         const float dy = min_image(Rx[a.ld + i] - y, a.j.L[1], a.j.Linv[1]);
         const float dz = min_image(Rx[2 * a.ld + i] - z, a.j.L[2], a.j.Linv[2]);
@@ -358,8 +366,8 @@ __global__ void jastrow_accept_kernel(float* R, int64_t ld, int64_t wstride, con
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
     const int kk = k[s];
-    if (kk < 0 || kk >= n_elec) return;
     const int64_t w = walkers ? (int64_t)walkers[s] : s;
+    if (kk < 0 || kk >= n_elec || w < 0) return;
     float* Rx = R + w * wstride;
     Rx[kk] = (float)rnew[3 * s];
     Rx[ld + kk] = (float)rnew[3 * s + 1];

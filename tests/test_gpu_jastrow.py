@@ -193,5 +193,29 @@ def test_edges(torch, q):
     out = J.move(Rd, kd[:1], torch.from_numpy(ion[None].astype(np.float32).astype(np.float64)).cuda()).cpu().numpy()
     ref = S.move(_f32(R[0]), 3, _f32(ion))
     assert np.all(np.isfinite(out)) and abs(out[0, 0] - ref[0]) < 1e-4
+    # a negative walker index (the C ABI directly: the binding refuses it first)
+    import ctypes
+    L = q.lib()
+    wl = torch.tensor([-1, 1], dtype=torch.int32, device="cuda")
+    kk = torch.tensor([3, 3], dtype=torch.int32, device="cuda")
+    r2 = torch.from_numpy(R[:, 5].astype(np.float64) + 0.01).cuda()
+    out = torch.empty((2, 5), dtype=torch.float32, device="cuda")
+    ld, ws = Rd.shape[-1], Rd.shape[-1] * 3
+    p = lambda x: ctypes.c_void_p(x.data_ptr())  # noqa: E731
+    assert L.jastrow_move(J._h, p(Rd), ld, ws, p(wl), p(kk), p(r2), 2, p(out), None) == 0
+    o = out.cpu().numpy()
+    assert np.all(np.isnan(o[0])) and np.all(np.isfinite(o[1]))
+    de = torch.empty((2, 16), dtype=torch.float32, device="cuda")
+    dre = torch.empty((2, 3, 16), dtype=torch.float32, device="cuda")
+    di = torch.empty((2, J.n_ion), dtype=torch.float32, device="cuda")
+    dri = torch.empty((2, 3, J.n_ion), dtype=torch.float32, device="cuda")
+    assert L.jastrow_dist_rows(J._h, p(Rd), ld, ws, p(wl), p(r2), 2, p(de), p(dre), p(di), p(dri), None) == 0
+    assert np.all(np.isnan(de[0].cpu().numpy())) and np.all(np.isnan(dre[0].cpu().numpy()))
+    assert np.all(np.isfinite(de[1].cpu().numpy())) and np.all(np.isfinite(di.cpu().numpy()))
+    before = Rd.clone()
+    assert L.jastrow_accept(J._h, p(Rd), ld, ws, p(wl), p(kk), p(r2), 2, None) == 0
+    after = Rd.cpu().numpy()
+    np.testing.assert_array_equal(after[0], before[0].cpu().numpy())  # walker -1 skipped, walker 0 untouched
+    assert not np.array_equal(after[1], before[1].cpu().numpy())
     with pytest.raises(q.SplineError):
         q.Jastrow((1.0, 1.0, 1.0), d["ions"], d["species"], [(d["f1"][0][0], 0.7)] * 2, d["uu"], d["ud"], 16, 8)
