@@ -131,6 +131,39 @@ int spline_eval_vgl(const spline_t* s, const double* pos_dev, int64_t B, void* V
  * Section 3): V device [B][n_orb], same conventions as spline_eval_vgl. */
 int spline_eval_v(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* stream);
 
+/* Locality-ordered evaluation of a large batch (the GPU counterpart of the
+ * table tiling of Section 8.4: positions, not the table, are reordered).
+ * The positions are bucketed on the device by the block of grid cells they
+ * fall in (blocks of 2^s cells per dimension, s chosen so there are at most
+ * 32 blocks per dimension; blocks in Morton order), then evaluated in that
+ * order, so positions that share table rows run together and re-read the
+ * rows from cache instead of HBM.  Inputs, outputs and conventions are those
+ * of spline_eval_vgl / spline_eval_v, and so are the results, bit for bit
+ * (each output row is written by the same per-position arithmetic; only the
+ * order of evaluation differs).  Pays when B is large against the grid (many
+ * positions per table row); costs four small extra launches.
+ *   workspace_dev  caller-owned device scratch, 256-byte aligned, at least
+ *                  spline_sorted_workspace_bytes(s, B) bytes (0 for a NULL
+ *                  handle or B outside [0, 2^31)); its contents on entry
+ *                  do not matter and are overwritten.
+ * Orthorhombic cells only (SPL_EUNSUPPORTED after spline_set_lattice);
+ * SPL_ENOMEM for a short workspace; B == 0 is a no-op.  Asynchronous on
+ * `stream`; calls that share a workspace must not overlap. */
+size_t spline_sorted_workspace_bytes(const spline_t* s, int64_t B);
+int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                           void* workspace_dev, size_t workspace_bytes, void* stream);
+int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
+                         size_t workspace_bytes, void* stream);
+/* The locality-ordered VGL path has its own tile shape (initially the VGL
+ * shape; the value-only path uses the value tile).  spline_autotune_sorted
+ * works as spline_autotune over that path (bitwise cross-check of every
+ * candidate, cache key with " sorted" appended) and selects the fastest. */
+int spline_set_sorted_tile(spline_t* s, const spline_tile* tile);
+int spline_get_sorted_tile(const spline_t* s, spline_tile* tile);
+int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                           void* workspace_dev, size_t workspace_bytes, int32_t reps, const char* cache_path,
+                           void* stream, spline_tile* chosen);
+
 /* Determinant ratio fused into the evaluation (Section 3: the ratio
  * equation and the matrix determinant lemma).  With A(i,j) = phi_i(r_j),
  * moving electron k to r'_k multiplies det A by sum_i Ainv(k,i) phi_i(r'_k),

@@ -62,6 +62,13 @@ def lib():
             "spline_create": ([p, i32, p, ctypes.c_int, p, sz, p, p], ctypes.c_int),
             "spline_eval_vgl": ([p, p, i64, p, p, p, p], ctypes.c_int),
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
+            "spline_sorted_workspace_bytes": ([p, i64], sz),
+            "spline_eval_vgl_sorted": ([p, p, i64, p, p, p, p, sz, p], ctypes.c_int),
+            "spline_eval_v_sorted": ([p, p, i64, p, p, sz, p], ctypes.c_int),
+            "spline_set_sorted_tile": ([p, p], ctypes.c_int),
+            "spline_get_sorted_tile": ([p, p], ctypes.c_int),
+            "spline_autotune_sorted": ([p, p, i64, p, p, p, p, sz, ctypes.c_int32, ctypes.c_char_p, p, p],
+                                       ctypes.c_int),
             "spline_eval_ratio_vgl": ([p, p, i64, p, i64, p, p, p], ctypes.c_int),
             "spline_det_update": ([p, i32, i64, p, p, p, i64, i64, ctypes.c_int, p], ctypes.c_int),
             "jastrow_bytes": ([p, p], sz),
@@ -282,6 +289,76 @@ class Spline:
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_v(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()), sp))
+        return V
+
+    def _sorted_ws(self, B: int, workspace):
+        nb = lib().spline_sorted_workspace_bytes(self._h, B)
+        if workspace is None:
+            ws = getattr(self, "_sws", None)
+            if ws is None or ws.numel() < nb:
+                ws = self._torch.empty(max(nb, 256), dtype=self._torch.uint8, device=self.device)
+                self._sws = ws
+            workspace = ws
+        if workspace.numel() < nb or workspace.device != self.device:
+            raise ValueError("workspace too small or on another device")
+        return ctypes.c_void_p(workspace.data_ptr()), workspace.numel()
+
+    def eval_vgl_sorted(self, pos, out=None, workspace=None, stream=None):
+        """eval_vgl in locality order (same results bit for bit, faster for
+        large batches); workspace: uint8 device tensor, kept on the object
+        when not given."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V, G, L = out if out is not None else self.alloc_outputs(B)
+        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (L, (B, self.norb))):
+            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("output tensor has wrong shape/dtype/device")
+        wp, wn = self._sorted_ws(B, workspace)
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_eval_vgl_sorted(self._h, ctypes.c_void_p(pos.data_ptr()), B,
+                                               ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                               ctypes.c_void_p(L.data_ptr()), wp, wn, sp))
+        return V, G, L
+
+    def set_sorted_tile(self, tile):
+        t = Tile(*tile)
+        check(lib().spline_set_sorted_tile(self._h, ctypes.byref(t)))
+
+    def get_sorted_tile(self):
+        t = Tile()
+        check(lib().spline_get_sorted_tile(self._h, ctypes.byref(t)))
+        return t.astuple()
+
+    def autotune_sorted(self, pos, reps: int = 5, cache_path: str | None = None, out=None, workspace=None,
+                        stream=None):
+        """Tile shape of the locality-ordered VGL path (see spline_autotune_sorted)."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V, G, L = out if out is not None else self.alloc_outputs(B)
+        wp, wn = self._sorted_ws(B, workspace)
+        t = Tile()
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_autotune_sorted(self._h, ctypes.c_void_p(pos.data_ptr()), B,
+                                               ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                               ctypes.c_void_p(L.data_ptr()), wp, wn, int(reps),
+                                               None if cache_path is None else cache_path.encode(), sp,
+                                               ctypes.byref(t)))
+        return t.astuple()
+
+    def eval_v_sorted(self, pos, out=None, workspace=None, stream=None):
+        """eval_v in locality order (same results bit for bit)."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V = out if out is not None else self._torch.empty((B, self.norb), dtype=self.out_dtype, device=self.device)
+        if tuple(V.shape) != (B, self.norb) or V.dtype != self.out_dtype or not V.is_contiguous():
+            raise ValueError("output tensor has wrong shape/dtype")
+        wp, wn = self._sorted_ws(B, workspace)
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_eval_v_sorted(self._h, ctypes.c_void_p(pos.data_ptr()), B,
+                                             ctypes.c_void_p(V.data_ptr()), wp, wn, sp))
         return V
 
     def set_lattice(self, lattice):

@@ -122,6 +122,10 @@ void set_general_args(const spline_s* s, EvalArgs& a);
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
 int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, void* G, void* H, int32_t reps,
                  hipStream_t st, spline_tile* chosen);
+// Tile validation and the tuning cache (spline_host.cpp).
+int check_tile(const spline_s* s, const spline_tile* t, bool vgl);
+std::string tune_key(const spline_s* s, int64_t B);
+bool cache_lookup(const char* path, const std::string& key, spline_tile* t);
 
 }  // namespace qs
 
@@ -136,6 +140,7 @@ struct spline_s {
     spline_tile tile;      // current VGL tile shape
     spline_tile vtile;     // current value-only tile shape
     spline_tile htile;     // current shape of the VGH family (also general-cell VGL)
+    spline_tile stile;     // current VGL tile shape of the locality-ordered path
     int general;           // 1 once a general lattice is set
     double lat[9];         // lattice vectors as rows (general cells)
     double ilat[9];        // its inverse

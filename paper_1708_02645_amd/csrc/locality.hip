@@ -1,0 +1,331 @@
+// Locality-ordered evaluation of a large batch.
+//
+// Each position needs the 4 x 4 x 4 table rows around its grid cell.  In a
+// batch of random positions consecutive workgroups touch unrelated rows, so
+// every gathered row comes from HBM.  Here the positions are first bucketed
+// by the block of 2^s x 2^s x 2^s grid cells they fall in, blocks in Morton
+// order (a counting sort on the device: key and rank within the bucket,
+// exclusive scan of the bucket sizes, scatter), and the evaluation kernel
+// then takes them in that order through its index list.  Positions that
+// share rows run close together in time, so most rows are re-read from the
+// L2 and Infinity caches instead of HBM.  Outputs go to each position's own
+// row and the per-position arithmetic is the evaluation kernel's, so the
+// results equal spline_eval_vgl / spline_eval_v bit for bit; the order
+// within a bucket (atomic ranks) changes only the timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <fstream>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace qs {
+
+constexpr int kLocThreads = 256;
+constexpr int kLocScanThreads = 1024;
+constexpr int kLocBits = 5;                            // coarse blocks per dimension <= 2^5
+constexpr int kLocBuckets = 1 << (3 * kLocBits);       // Morton keys < 2^15
+
+struct LocKey {
+    double inv[3];    // 1 / cell length
+    int32_t n[3];     // grid points per dimension
+    int32_t shift;    // coarse block = 2^shift cells per dimension
+};
+
+// The low ten bits of v moved to every third bit position (Morton interleave).
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(kLocThreads) void loc_zero_kernel(int32_t* count, int n)
+{
+    const int i = blockIdx.x * kLocThreads + threadIdx.x;
+    if (i < n) count[i] = 0;
+}
+
+// Bucket of each position and its rank among the positions of that bucket.
+// A non-finite coordinate goes to block 0 (the evaluation kernel gives its
+// outputs NaN either way).
+__global__ __launch_bounds__(kLocThreads) void loc_key_kernel(const double* pos, int64_t B, LocKey k, int32_t* count,
+                                                              int32_t* key, int32_t* rank)
+{
+    const int64_t b = (int64_t)blockIdx.x * kLocThreads + threadIdx.x;
+    if (b >= B) return;
+    uint32_t c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double u = pos[3 * b + d] * k.inv[d];
+        u -= floor(u);
+        int i = (u >= 0.0 && u < 1.0) ? (int)(u * k.n[d]) : 0;
+        i = i < 0 ? 0 : (i >= k.n[d] ? k.n[d] - 1 : i);
+        c[d] = (uint32_t)i >> k.shift;
+    }
+    const int32_t kk = (int32_t)((spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]));
+    key[b] = kk;
+    rank[b] = atomicAdd(&count[kk], 1);
+}
+
+// Exclusive prefix sum of count[0 .. kLocBuckets) in place, one workgroup:
+// each thread sums a run of buckets, the runs' totals are scanned in LDS,
+// then every thread writes its run's offsets.
+__global__ __launch_bounds__(kLocScanThreads) void loc_scan_kernel(int32_t* count)
+{
+    constexpr int kRun = kLocBuckets / kLocScanThreads;
+    __shared__ int32_t part[kLocScanThreads];
+    const int t = threadIdx.x;
+    int32_t v[kRun];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) {
+        v[i] = count[t * kRun + i];
+        s += v[i];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kLocScanThreads; off <<= 1) {  // inclusive scan of the run totals
+        const int32_t x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int32_t run = part[t] - s;  // exclusive start of this thread's run
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) {
+        count[t * kRun + i] = run;
+        run += v[i];
+    }
+}
+
+// Sorted slot j = offset[key] + rank goes to the index list so that the
+// workgroups on one XCD take a contiguous stretch of the sorted order:
+// workgroups are dispatched to the eight XCDs in turn (workgroup i to XCD
+// i mod 8), so whole chunks of pb slots are dealt out as chunk c -> workgroup
+// 8k + x, where x is the XCD whose contiguous share of the chunks holds c and
+// k is c's place in it.  The chunks of one XCD then share table rows in that
+// XCD's L2.  A partial last chunk stays last (only the last workgroup takes
+// fewer than pb positions).
+__global__ __launch_bounds__(kLocThreads) void loc_scatter_kernel(int64_t B, int32_t pb, const int32_t* offset,
+                                                                  const int32_t* key, const int32_t* rank,
+                                                                  int32_t* perm)
+{
+    const int64_t b = (int64_t)blockIdx.x * kLocThreads + threadIdx.x;
+    if (b >= B) return;
+    const int64_t j = (int64_t)offset[key[b]] + rank[b];
+    const int64_t full = B / pb, c = j / pb, r = j - c * pb;
+    int64_t dst = j;
+    if (c < full) {
+        const int64_t c8 = full / 8, rem = full % 8, big = rem * (c8 + 1);  // XCDs x < rem take c8 + 1 chunks
+        int64_t x, k;
+        if (c < big) {
+            x = c / (c8 + 1);
+            k = c - x * (c8 + 1);
+        } else {  // then c8 >= 1
+            const int64_t e = c - big;
+            x = rem + e / c8;
+            k = e - (x - rem) * c8;
+        }
+        dst = (8 * k + x) * pb + r;
+    }
+    perm[dst] = (int32_t)b;
+}
+
+static_assert(kLocBuckets % kLocScanThreads == 0, "scan runs must tile the buckets");
+
+// Workspace: count [kLocBuckets], key [B], rank [B], perm [B], int32 each.
+static size_t loc_bytes(int64_t B)
+{
+    const size_t words = (size_t)kLocBuckets + 3 * (size_t)B;
+    return (words * 4 + 255) & ~(size_t)255;
+}
+
+static int sorted_check(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, void* ws,
+                        size_t ws_bytes, bool vgl)
+{
+    if (!s) return fail(SPL_EINVAL, "handle is NULL");
+    if (B < 0 || B > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(SPL_EINVAL, "B must be in [0, 2^31)");
+    if (B == 0) return SPL_OK;
+    if (!pos || !V || (vgl && (!G || !L))) return fail(SPL_EINVAL, "NULL position or output pointer");
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(SPL_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < loc_bytes(B)) return fail(SPL_ENOMEM, "workspace smaller than spline_sorted_workspace_bytes()");
+    int64_t tmp;
+    if (!mul_ok(B, (int64_t)s->norb * 3 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    if (s->general) return fail(SPL_EUNSUPPORTED, "locality-ordered evaluation is built for orthorhombic cells");
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev != s->device) return fail(SPL_EINVAL, "current HIP device differs from the table's device");
+    return SPL_OK;
+}
+
+// The sort (four small launches) and the evaluation with tile t; arguments
+// already checked.
+static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const double* pos, int64_t B, void* V,
+                      void* G, void* L, void* ws, hipStream_t st)
+{
+    const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl);
+    if (!v) return fail(SPL_EUNSUPPORTED, "tile shape not compiled");
+    LocKey k;
+    int bits = 0;
+    for (int d = 0; d < 3; ++d) {
+        k.inv[d] = 1.0 / s->grid.cell[d];
+        k.n[d] = s->grid.n[d];
+        int bd = 0;
+        while ((1 << bd) < s->grid.n[d]) ++bd;
+        bits = bd > bits ? bd : bits;
+    }
+    k.shift = bits > kLocBits ? bits - kLocBits : 0;
+    int32_t* count = static_cast<int32_t*>(ws);
+    int32_t* key = count + kLocBuckets;
+    int32_t* rank = key + B;
+    int32_t* perm = rank + B;
+    const unsigned gb = (unsigned)((B + kLocThreads - 1) / kLocThreads);
+    hipLaunchKernelGGL(loc_zero_kernel, dim3(kLocBuckets / kLocThreads), dim3(kLocThreads), 0, st, count,
+                       kLocBuckets);
+    hipLaunchKernelGGL(loc_key_kernel, dim3(gb), dim3(kLocThreads), 0, st, pos, B, k, count, key, rank);
+    hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(kLocScanThreads), 0, st, count);
+    hipLaunchKernelGGL(loc_scatter_kernel, dim3(gb), dim3(kLocThreads), 0, st, B, (int32_t)t.pb, count, key, rank,
+                       perm);
+    QS_HIP(hipGetLastError());
+    EvalArgs a = make_args(s, t, pos, B, V, G, L);
+    a.idx = perm;
+    return launch(*v, a, st);
+}
+
+static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, void* ws,
+                         size_t ws_bytes, void* stream, bool vgl)
+{
+    int rc = sorted_check(s, pos, B, V, G, L, ws, ws_bytes, vgl);
+    if (rc || B == 0) return rc;
+    return sorted_run(s, vgl ? s->stile : s->vtile, vgl, pos, B, V, G, L, ws, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+extern "C" {
+
+size_t spline_sorted_workspace_bytes(const spline_t* s, int64_t B)
+{
+    if (!s || B < 0 || B > (int64_t)std::numeric_limits<int32_t>::max()) return 0;
+    return loc_bytes(B);
+}
+
+int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                           void* workspace_dev, size_t workspace_bytes, void* stream)
+{
+    return sorted_common(s, pos_dev, B, V, G, L, workspace_dev, workspace_bytes, stream, true);
+}
+
+int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
+                         size_t workspace_bytes, void* stream)
+{
+    return sorted_common(s, pos_dev, B, V, nullptr, nullptr, workspace_dev, workspace_bytes, stream, false);
+}
+
+int spline_set_sorted_tile(spline_t* s, const spline_tile* tile)
+{
+    if (!s) return fail(SPL_EINVAL, "handle is NULL");
+    const int rc = check_tile(s, tile, true);
+    if (rc) return rc;
+    s->stile = *tile;
+    return SPL_OK;
+}
+
+int spline_get_sorted_tile(const spline_t* s, spline_tile* tile)
+{
+    if (!s || !tile) return fail(SPL_EINVAL, "NULL argument");
+    *tile = s->stile;
+    return SPL_OK;
+}
+
+// As spline_autotune, over the locality-ordered VGL path: every candidate's
+// outputs on the first positions must equal the first candidate's bit for
+// bit; cache lines "<key> sorted|cw nch lpp pb".
+int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                           void* workspace_dev, size_t workspace_bytes, int32_t reps, const char* cache_path,
+                           void* stream, spline_tile* chosen)
+{
+    int rc = sorted_check(s, pos_dev, B, V, G, L, workspace_dev, workspace_bytes, true);
+    if (rc) return rc;
+    if (B == 0) return fail(SPL_EINVAL, "autotune needs a non-empty batch");
+    if (reps < 1) reps = 1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::string key = tune_key(s, B) + " sorted";
+    spline_tile best_t{};
+    if (cache_path && cache_lookup(cache_path, key, &best_t) && check_tile(s, &best_t, true) == SPL_OK) {
+        s->stile = best_t;
+        if (chosen) *chosen = best_t;
+        return SPL_OK;
+    }
+    int32_t n = 0;
+    rc = spline_tile_candidates(s, nullptr, 0, &n);
+    if (rc) return rc;
+    std::vector<spline_tile> cands(n);
+    spline_tile_candidates(s, cands.data(), n, &n);
+    if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
+    const int64_t Bc = std::min<int64_t>(B, 512);
+    const size_t nv = (size_t)Bc * s->norb * (s->store == SPL_F64 ? 8 : 4);
+    std::vector<unsigned char> ref, cur(5 * nv);
+    hipEvent_t e0, e1;
+    QS_HIP(hipEventCreate(&e0));
+    QS_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    best_t = cands[0];
+    for (int i = 0; i < n && rc == SPL_OK; ++i) {
+        const spline_tile t = cands[i];
+        rc = sorted_run(s, t, true, pos_dev, B, V, G, L, workspace_dev, st);
+        if (rc) break;
+        if (hipMemcpyAsync(cur.data(), V, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(cur.data() + nv, G, 3 * nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(cur.data() + 4 * nv, L, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(SPL_EHIP, "autotune: copy of outputs failed");
+            break;
+        }
+        if (ref.empty()) {
+            ref = cur;
+        } else if (std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
+            rc = fail(SPL_EUNSUPPORTED, "autotune: a tile shape differs bitwise from the first candidate");
+            break;
+        }
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            rc = fail(SPL_EHIP, "event record");
+            break;
+        }
+        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = sorted_run(s, t, true, pos_dev, B, V, G, L, workspace_dev, st);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(SPL_EHIP, "autotune: event timing failed");
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    s->stile = best_t;
+    if (chosen) *chosen = best_t;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (f) f << key << "|" << best_t.cw << " " << best_t.nch << " " << best_t.lpp << " " << best_t.pb << "\n";
+    }
+    return SPL_OK;
+}
+
+}  // extern "C"

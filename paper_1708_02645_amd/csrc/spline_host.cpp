@@ -327,7 +327,7 @@ static spline_tile default_tile(const spline_s* s, bool vgl)
     return best;
 }
 
-static int check_tile(const spline_s* s, const spline_tile* t, bool vgl)
+int check_tile(const spline_s* s, const spline_tile* t, bool vgl)
 {
     if (!t) return fail(SPL_EINVAL, "tile is NULL");
     if (t->pb < 1 || t->pb > 256) return fail(SPL_EINVAL, "positions per workgroup must be in [1, 256]");
@@ -414,6 +414,7 @@ int spline_create(const spline_grid* grid, int32_t n_orb, const double* coefs_ho
     s->tile = default_tile(s, true);
     s->vtile = default_tile(s, false);
     s->htile = default_vgh_tile(s);
+    s->stile = s->tile;
     s->general = 0;
     if (s->tile.cw == 0 || s->vtile.cw == 0 || s->htile.cw == 0) {
         delete s;
@@ -561,7 +562,7 @@ int spline_get_value_tile(const spline_t* s, spline_tile* tile)
 
 namespace qs {
 
-static std::string tune_key(const spline_s* s, int64_t B)
+std::string tune_key(const spline_s* s, int64_t B)
 {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
@@ -578,7 +579,7 @@ static std::string tune_key(const spline_s* s, int64_t B)
     return k.str();
 }
 
-static bool cache_lookup(const char* path, const std::string& key, spline_tile* t)
+bool cache_lookup(const char* path, const std::string& key, spline_tile* t)
 {
     std::ifstream f(path);
     if (!f) return false;

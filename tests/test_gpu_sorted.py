@@ -1,0 +1,139 @@
+"""Locality-ordered evaluation (spline_eval_vgl_sorted / spline_eval_v_sorted)
+must give exactly the results of the plain entry points: the same
+per-position arithmetic, only in another order.  Outputs are pre-filled with
+NaN, so a position the sort dropped would show.  The small case is also
+checked against the FP64 oracle; the full-size case runs the 80^3 / N=384
+table on the 512 x 384 batch in the launch configuration the bench times.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def q(torch):
+    import paper_1708_02645_amd as qq
+    qq.lib()
+    return qq
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _nan_outputs(torch, s, B):
+    V, G, L = s.alloc_outputs(B)
+    for t in (V, G, L):
+        t.fill_(float("nan"))
+    return V, G, L
+
+
+def _same(torch, a, b):
+    for x, y in zip(a, b):
+        assert torch.equal(x, y) or bool(((x == y) | (torch.isnan(x) & torch.isnan(y))).all())
+
+
+def _check_equal(torch, s, pos_np):
+    pos = torch.from_numpy(pos_np).cuda()
+    B = pos.shape[0]
+    ref = s.eval_vgl(pos)
+    got = s.eval_vgl_sorted(pos, out=_nan_outputs(torch, s, B))
+    _same(torch, got, ref)
+    v_ref = s.eval_v(pos)
+    v = torch.full_like(v_ref, float("nan"))
+    s.eval_v_sorted(pos, out=v)
+    _same(torch, (v,), (v_ref,))
+    return got
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_small_table_equal_and_against_oracle(torch, q, oracle, dtype):
+    grid, N, coefs, _ = W.make_table(1)  # 16^3, 32 orbitals
+    s = q.Spline(grid, coefs, dtype)
+    pos = W.make_positions(1)  # 1000 positions
+    _say("case sorted small", dtype)
+    V, G, L = _check_equal(torch, s, pos)
+    deq = coefs if dtype == "f64" else oracle.dequantize(coefs, dtype)[0]
+    ref = oracle.eval_vgl(grid, deq, pos)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for name, a, b in zip("VGL", (V, G, L), ref):
+        e = oracle.rel_err(a.cpu().numpy(), b)
+        assert e <= tol, "%s %s: %.3e" % (dtype, name, e)
+
+
+def test_edges(torch, q):
+    rng = np.random.default_rng(3)
+    grid = (7, 9, 11)
+    coefs = rng.uniform(-1, 1, grid + (40,))
+    s = q.Spline(grid, coefs, "f32", cell=(1.3, 0.7, 2.1))
+    for B in (1, 17, 300):
+        _say("case sorted edge B", B)
+        pos = rng.uniform(-40, 40, (B, 3))  # far outside the cell: periodic wrap
+        if B == 300:
+            pos[5] = np.nan
+            pos[6, 1] = np.inf
+        _check_equal(torch, s, pos)
+    # B == 0 is a no-op; a short workspace and a general cell are refused
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    s.eval_vgl_sorted(e)
+    pos = torch.from_numpy(rng.random((64, 3))).cuda()
+    with pytest.raises(ValueError):
+        s.eval_vgl_sorted(pos, workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    L = q.lib()
+    assert L.spline_sorted_workspace_bytes(None, 10) == 0
+    assert L.spline_sorted_workspace_bytes(s._h, -1) == 0
+    assert L.spline_sorted_workspace_bytes(s._h, 10) % 256 == 0
+    s.set_lattice([[1.3, 0, 0], [0.2, 0.7, 0], [0, 0, 2.1]])
+    with pytest.raises(q.SplineError):
+        s.eval_vgl_sorted(pos)
+
+
+def test_tiles_and_chunk_dealing(torch, q):
+    """The index list deals whole chunks of pb sorted slots to the XCDs;
+    every tile (pb 16, 32, 64) and batch size (no whole chunk, a partial last
+    chunk, chunk counts that do and do not divide by 8) must still cover each
+    position exactly once."""
+    rng = np.random.default_rng(11)
+    grid = (12, 10, 9)
+    s = q.Spline(grid, rng.uniform(-1, 1, grid + (64,)), "f32")
+    seen = {}
+    for t in s.tile_candidates():
+        seen.setdefault(t[3], t)
+    assert len(seen) >= 2
+    for pb, t in sorted(seen.items()):
+        s.set_sorted_tile(t)
+        assert tuple(s.get_sorted_tile()) == tuple(t)
+        for B in (5, 1000, 16 * 8 * 3, 4099):
+            _say("case sorted tile", t, "B", B)
+            _check_equal(torch, s, rng.random((B, 3)))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_full_size_equal(torch, q, dtype):
+    """80^3 grid, 384 orbitals, 196,608 positions (the bench's batch)."""
+    grid, N, coefs, _ = W.make_table(3)
+    s = q.Spline(grid, coefs, dtype)
+    del coefs
+    pos = W.make_positions(3)
+    import os
+    cache = os.path.join(os.path.dirname(q.__file__), "tune_cache.txt")
+    s.autotune(torch.from_numpy(pos).cuda(), reps=2, cache_path=cache)  # the bench's tile (cached)
+    _say("case sorted full", dtype, pos.shape, s.get_tile())
+    _check_equal(torch, s, pos)
+    t = s.autotune_sorted(torch.from_numpy(pos).cuda(), reps=1)  # no cache: searches, cross-checks bitwise
+    _say("case sorted full tuned", dtype, t)
+    _check_equal(torch, s, pos)
