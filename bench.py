@@ -38,6 +38,7 @@ def log(*a):
 
 
 VGH_SOURCES = KERNEL_SOURCES + ["paper_1708_02645_amd/csrc/vgh_kernel.hpp", "paper_1708_02645_amd/csrc/vgh_f32.hip"]
+SORTED_SOURCES = KERNEL_SOURCES + ["paper_1708_02645_amd/csrc/locality.hip"]
 
 
 def kernel_hash(sources=None) -> str:
@@ -57,7 +58,7 @@ def traffic_from_profiles(tile, name: str = "vgl_f32_80cube_n384") -> float | No
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    srcs = VGH_SOURCES if name.startswith("vgh") else KERNEL_SOURCES
+    srcs = VGH_SOURCES if name.startswith("vgh") else SORTED_SOURCES if "sorted" in name else KERNEL_SOURCES
     if d.get("kernel_hash") != kernel_hash(srcs) or tuple(d.get("tile", ())) != tuple(tile):
         return None
     return d.get("hbm_bytes_per_launch")
@@ -166,6 +167,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")
     ap.add_argument("--vgh-tile", type=str, default="", help="cw,nch,lpp,pb for the VGH forms (skips their autotuner)")
+    ap.add_argument("--sorted-tile", type=str, default="",
+                    help="cw,nch,lpp,pb for the FP32 locality-ordered form (skips its autotuner)")
     ap.add_argument("--no-tune-cache", dest="use_tune_cache", action="store_false",
                     help="search tile shapes afresh instead of reading the committed tuning cache")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -262,6 +265,26 @@ def main() -> int:
     # value only (the quadrature-point evaluation): same table and positions
     ms_v, _ = time_steps(torch, lambda: s32.eval_v(pos, out=out32[0]), args.steps, args.warmup)
     vtile32 = s32.get_value_tile()
+
+    # Locality-ordered evaluation of the same batch: positions bucketed on the
+    # device by Morton-ordered blocks of grid cells, then evaluated in that
+    # order (the sort is inside the timed step); same outputs bit for bit.
+    def bench_sorted(s, out, tile_arg):
+        if tile_arg:
+            s.set_sorted_tile(tile_arg)
+            st = tuple(tile_arg)
+        else:
+            st = s.autotune_sorted(pos, reps=3, out=out, cache_path=TUNE_CACHE if args.use_tune_cache else None)
+        ms, _ = time_steps(torch, lambda: s.eval_vgl_sorted(pos, out=out), args.steps, args.warmup)
+        plain = s.eval_vgl(pos)
+        same = all(bool(torch.equal(a, b)) for a, b in zip(out, plain))
+        del plain
+        torch.cuda.empty_cache()
+        log("bench: %s locality-ordered tile %s  %.3f ms/step  bitwise equal: %s" % (s.dtype, st, ms, same))
+        return st, ms, same
+
+    stile_arg = tuple(int(x) for x in args.sorted_tile.split(",")) if args.sorted_tile else None
+    stile32, ms_sorted, same32 = bench_sorted(s32, out32, stile_arg)
     del out32
     torch.cuda.empty_cache()
 
@@ -370,6 +393,15 @@ def main() -> int:
                                     "note": "each move: ratio against the pending moves + accept; one flush per "
                                             "16 moves (all included); _graph: the 16 moves and the flush replayed "
                                             "from one HIP graph"},
+             "f32_locality_sorted": {
+                 "evals_per_s": units / (ms_sorted * 1e-3), "ms_per_step": ms_sorted, "tile": list(stile32),
+                 "speedup_vs_f32": ms32 / ms_sorted, "bitwise_equal_to_f32": same32,
+                 "algorithmic_GBs": units * BYTES_PER_UNIT["f32"] / (ms_sorted * 1e-3) / 1e9,
+                 "traffic": traffic_from_profiles(stile32, "vgl_sorted_f32_80cube_n384"),
+                 "note": "same batch and outputs; positions bucketed by Morton-ordered 4^3-cell blocks on the "
+                         "device (4 small launches, timed) and dealt so each XCD takes a contiguous stretch, so "
+                         "table rows are re-read from L2 / Infinity Cache: the algorithmic bytes exceed what "
+                         "HBM moves"},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}
@@ -380,6 +412,10 @@ def main() -> int:
             forms[dt] = {"evals_per_s": units / (ms * 1e-3), "ms_per_step": ms, "tile": list(t),
                          "speedup_vs_f32": ms32 / ms, "eps_V": e[0], "eps_G": e[1], "eps_L": e[2],
                          "hbm_frac": units * BYTES_PER_UNIT[dt] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+            st, mss, same = bench_sorted(s, out, None)
+            forms[dt + "_locality_sorted"] = {"evals_per_s": units / (mss * 1e-3), "ms_per_step": mss,
+                                              "tile": list(st), "speedup_vs_f32": ms32 / mss,
+                                              "bitwise_equal_to_" + dt: same}
             del s, out
             torch.cuda.empty_cache()
 
