@@ -309,6 +309,12 @@ def main() -> int:
     rit = torch.from_numpy(ridx).to(dev)
     eps_ratio = float(np.max(np.abs(Dbuf[rit].double().cpu().numpy() - Dref) / rscale))
     eps_ratio_v = float(np.max(np.abs(Rbuf[rit].double().cpu().numpy() - Dref[:, 0]) / sv))
+    # the same in locality order (sorted tile shape for the ratio with derivatives)
+    ms_rvgl_s, _ = time_steps(torch, lambda: s32.eval_ratio_vgl_sorted(pos, rows_d, out=Dbuf), args.steps,
+                              args.warmup)
+    ms_rv_s, _ = time_steps(torch, lambda: s32.eval_ratio_v_sorted(pos, rows_d, out=Rbuf), args.steps, args.warmup)
+    eps_ratio_s = float(np.max(np.abs(Dbuf[rit].double().cpu().numpy() - Dref) / rscale))
+    eps_ratio_v_s = float(np.max(np.abs(Rbuf[rit].double().cpu().numpy() - Dref[:, 0]) / sv))
     # Sherman-Morrison update after one accepted move per walker: the 512
     # stacked 384 x 384 FP32 inverses above (their rows stand in for A^-1),
     # electron k_w = w mod 384, unit-variance orbital values.
@@ -402,6 +408,12 @@ def main() -> int:
                          "device (4 small launches, timed) and dealt so each XCD takes a contiguous stretch, so "
                          "table rows are re-read from L2 / Infinity Cache: the algorithmic bytes exceed what "
                          "HBM moves"},
+             "f32_ratio_vgl_locality_sorted": {"evals_per_s": units / (ms_rvgl_s * 1e-3), "ms_per_step": ms_rvgl_s,
+                                               "tile": list(stile32), "speedup_vs_f32_ratio_vgl": ms_rvgl / ms_rvgl_s,
+                                               "eps": eps_ratio_s},
+             "f32_ratio_v_locality_sorted": {"evals_per_s": units / (ms_rv_s * 1e-3), "ms_per_step": ms_rv_s,
+                                             "tile": list(vtile32), "speedup_vs_f32_ratio_v": ms_rv / ms_rv_s,
+                                             "eps": eps_ratio_v_s},
              "f32_ratio_v": {"evals_per_s": units / (ms_rv * 1e-3), "ms_per_step": ms_rv, "tile": list(vtile32),
                              "hbm_frac": units * bpu_rv / (ms_rv * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "bytes_per_unit": bpu_rv, "eps": eps_ratio_v}}

@@ -154,6 +154,18 @@ int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
                            void* workspace_dev, size_t workspace_bytes, void* stream);
 int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
                          size_t workspace_bytes, void* stream);
+/* The fused determinant ratio in locality order: arguments and errors of
+ * spline_eval_ratio_vgl / spline_eval_ratio_v, plus the workspace of
+ * spline_eval_vgl_sorted.  Uses the sorted tile shape (the value tile for
+ * the ratio alone).  The order of the ratio's partial sums depends on the
+ * tile shape, so the results equal those of the plain entry point run with
+ * the same shape, bit for bit (and differ from other shapes by rounding). */
+int spline_eval_ratio_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                                 int64_t ld, const int32_t* rows_dev, void* D, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream);
+int spline_eval_ratio_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                               int64_t ld, const int32_t* rows_dev, void* R, void* workspace_dev,
+                               size_t workspace_bytes, void* stream);
 /* The locality-ordered VGL path has its own tile shape (initially the VGL
  * shape; the value-only path uses the value tile).  spline_autotune_sorted
  * works as spline_autotune over that path (bitwise cross-check of every

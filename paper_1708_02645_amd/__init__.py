@@ -65,6 +65,8 @@ def lib():
             "spline_sorted_workspace_bytes": ([p, i64], sz),
             "spline_eval_vgl_sorted": ([p, p, i64, p, p, p, p, sz, p], ctypes.c_int),
             "spline_eval_v_sorted": ([p, p, i64, p, p, sz, p], ctypes.c_int),
+            "spline_eval_ratio_vgl_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
+            "spline_eval_ratio_v_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
             "spline_set_sorted_tile": ([p, p], ctypes.c_int),
             "spline_get_sorted_tile": ([p, p], ctypes.c_int),
             "spline_autotune_sorted": ([p, p, i64, p, p, p, p, sz, ctypes.c_int32, ctypes.c_char_p, p, p],
@@ -423,7 +425,7 @@ class Spline:
                                             ctypes.c_void_p(H.data_ptr()), reps, sp, ctypes.byref(t)))
         return t.astuple()
 
-    def _ratio(self, vgl, pos, ainv, ld, rows, out, stream):
+    def _ratio(self, vgl, pos, ainv, ld, rows, out, stream, sorted_ws=None):
         torch = self._torch
         pos = self._pos(pos)
         B = pos.shape[0]
@@ -448,13 +450,25 @@ class Spline:
         D = out if out is not None else torch.empty(shape, dtype=self.out_dtype, device=self.device)
         if tuple(D.shape) != shape or D.dtype != self.out_dtype or not D.is_contiguous() or D.device != self.device:
             raise ValueError("output tensor must be a contiguous %s %s tensor" % (self.out_dtype, shape))
-        fn = lib().spline_eval_ratio_vgl if vgl else lib().spline_eval_ratio_v
+        args = [self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(ainv.data_ptr()), ld,
+                ctypes.c_void_p(rows.data_ptr()) if rows is not None else None, ctypes.c_void_p(D.data_ptr())]
+        if sorted_ws is not False and sorted_ws is not None:
+            fn = lib().spline_eval_ratio_vgl_sorted if vgl else lib().spline_eval_ratio_v_sorted
+            args += list(self._sorted_ws(B, None if sorted_ws is True else sorted_ws))
+        else:
+            fn = lib().spline_eval_ratio_vgl if vgl else lib().spline_eval_ratio_v
         with torch.cuda.device(self.device):
             sp, _ = _stream_ptr(torch, self.device, stream)
-            check(fn(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(ainv.data_ptr()), ld,
-                     ctypes.c_void_p(rows.data_ptr()) if rows is not None else None, ctypes.c_void_p(D.data_ptr()),
-                     sp))
+            check(fn(*args, sp))
         return D
+
+    def eval_ratio_vgl_sorted(self, pos, ainv, ld=None, rows=None, out=None, workspace=None, stream=None):
+        """eval_ratio_vgl in locality order (same results bit for bit)."""
+        return self._ratio(True, pos, ainv, ld, rows, out, stream, workspace if workspace is not None else True)
+
+    def eval_ratio_v_sorted(self, pos, ainv, ld=None, rows=None, out=None, workspace=None, stream=None):
+        """eval_ratio_v in locality order (same results bit for bit)."""
+        return self._ratio(False, pos, ainv, ld, rows, out, stream, workspace if workspace is not None else True)
 
     def eval_ratio_vgl(self, pos, ainv, ld=None, rows=None, out=None, stream=None):
         """D[B,5]: dot products of each position's row of A^-1 with the orbital

@@ -167,13 +167,11 @@ static int sorted_check(const spline_s* s, const double* pos, int64_t B, void* V
     return SPL_OK;
 }
 
-// The sort (four small launches) and the evaluation with tile t; arguments
-// already checked.
-static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const double* pos, int64_t B, void* V,
-                      void* G, void* L, void* ws, hipStream_t st)
+// The sort (four small launches) for workgroups of pb positions; returns
+// the index list inside the workspace.
+static int sort_positions(const spline_s* s, const double* pos, int64_t B, int pb, void* ws, hipStream_t st,
+                          const int32_t** perm_out)
 {
-    const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl);
-    if (!v) return fail(SPL_EUNSUPPORTED, "tile shape not compiled");
     LocKey k;
     int bits = 0;
     for (int d = 0; d < 3; ++d) {
@@ -193,9 +191,22 @@ static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const d
                        kLocBuckets);
     hipLaunchKernelGGL(loc_key_kernel, dim3(gb), dim3(kLocThreads), 0, st, pos, B, k, count, key, rank);
     hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(kLocScanThreads), 0, st, count);
-    hipLaunchKernelGGL(loc_scatter_kernel, dim3(gb), dim3(kLocThreads), 0, st, B, (int32_t)t.pb, count, key, rank,
+    hipLaunchKernelGGL(loc_scatter_kernel, dim3(gb), dim3(kLocThreads), 0, st, B, (int32_t)pb, count, key, rank,
                        perm);
     QS_HIP(hipGetLastError());
+    *perm_out = perm;
+    return SPL_OK;
+}
+
+// The sort and the evaluation with tile t; arguments already checked.
+static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const double* pos, int64_t B, void* V,
+                      void* G, void* L, void* ws, hipStream_t st)
+{
+    const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl);
+    if (!v) return fail(SPL_EUNSUPPORTED, "tile shape not compiled");
+    const int32_t* perm = nullptr;
+    int rc = sort_positions(s, pos, B, t.pb, ws, st, &perm);
+    if (rc) return rc;
     EvalArgs a = make_args(s, t, pos, B, V, G, L);
     a.idx = perm;
     return launch(*v, a, st);
@@ -231,6 +242,55 @@ int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, vo
                          size_t workspace_bytes, void* stream)
 {
     return sorted_common(s, pos_dev, B, V, nullptr, nullptr, workspace_dev, workspace_bytes, stream, false);
+}
+
+// Determinant ratio in locality order: as spline_eval_ratio_vgl / _v (the
+// row of A^-1 for position b is still ainv + (rows ? rows[b] : b) * ld), with
+// the sorted tile shape (the value tile for the ratio alone).  The ratio's
+// partial sums follow the tile shape, so the results equal the plain entry
+// point's under the same shape.  Positions per workgroup are halved until
+// the per-tile partial sums fit in LDS.
+static int sorted_ratio(const spline_s* s, const double* pos, int64_t B, const void* ainv, int64_t ld,
+                        const int32_t* rows, void* D, void* ws, size_t ws_bytes, void* stream, bool vgl)
+{
+    if (!s) return fail(SPL_EINVAL, "handle is NULL");
+    if (ld < 0) return fail(SPL_EINVAL, "ld must be >= 0");
+    int rc = sorted_check(s, pos, B, D, D, D, ws, ws_bytes, false);
+    if (rc || B == 0) return rc;
+    if (!ainv) return fail(SPL_EINVAL, "NULL inverse-row pointer");
+    const uintptr_t eb = s->store == SPL_F64 ? 8 : 4;
+    if ((uintptr_t)ainv % eb || (uintptr_t)D % eb)
+        return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
+    spline_tile t = vgl ? s->stile : s->vtile;
+    const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
+    if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");
+    const int64_t tiles = tiles_of(s, t);
+    while (t.pb > 1 && launch_lds(*v, t.pb, tiles) > kMaxLds) t.pb /= 2;
+    if (launch_lds(*v, t.pb, tiles) > kMaxLds) return fail(SPL_EUNSUPPORTED, "row too wide for the partial sums");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t* perm = nullptr;
+    rc = sort_positions(s, pos, B, t.pb, ws, st, &perm);
+    if (rc) return rc;
+    EvalArgs a = make_args(s, t, pos, B, D, nullptr, nullptr);
+    a.ainv = ainv;
+    a.ald = ld;
+    a.arows = rows;
+    a.idx = perm;
+    return launch(*v, a, st);
+}
+
+int spline_eval_ratio_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                                 int64_t ld, const int32_t* rows_dev, void* D, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream)
+{
+    return sorted_ratio(s, pos_dev, B, ainv_dev, ld, rows_dev, D, workspace_dev, workspace_bytes, stream, true);
+}
+
+int spline_eval_ratio_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
+                               int64_t ld, const int32_t* rows_dev, void* R, void* workspace_dev,
+                               size_t workspace_bytes, void* stream)
+{
+    return sorted_ratio(s, pos_dev, B, ainv_dev, ld, rows_dev, R, workspace_dev, workspace_bytes, stream, false);
 }
 
 int spline_set_sorted_tile(spline_t* s, const spline_tile* tile)

@@ -137,3 +137,41 @@ def test_full_size_equal(torch, q, dtype):
     t = s.autotune_sorted(torch.from_numpy(pos).cuda(), reps=1)  # no cache: searches, cross-checks bitwise
     _say("case sorted full tuned", dtype, t)
     _check_equal(torch, s, pos)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_ratio_small_equal(torch, q, dtype):
+    """Determinant ratio in locality order equals the plain entry points bit
+    for bit: rows of stacked inverses (no row list), and a row list with
+    repeated rows (quadrature points sharing an electron)."""
+    grid, N, coefs, _ = W.make_table(1)
+    s = q.Spline(grid, coefs, dtype)
+    rng = np.random.default_rng(21)
+    B = 1000
+    pos = torch.from_numpy(W.make_positions(1)).cuda()
+    ainv = torch.from_numpy(rng.normal(size=(B, N)) / np.sqrt(N)).to(s.out_dtype).cuda()
+    rows = torch.from_numpy(rng.integers(0, B, B).astype(np.int32)).cuda()
+    s.set_sorted_tile(s.get_tile())  # the ratio's sums follow the tile shape: compare under one shape
+    for r in (None, rows):
+        _say("case sorted ratio", dtype, r is None)
+        _same(torch, (s.eval_ratio_vgl_sorted(pos, ainv, rows=r),), (s.eval_ratio_vgl(pos, ainv, rows=r),))
+        _same(torch, (s.eval_ratio_v_sorted(pos, ainv, rows=r),), (s.eval_ratio_v(pos, ainv, rows=r),))
+
+
+def test_ratio_full_size_equal(torch, q):
+    """80^3 / N=384 / 196,608 positions, rows of the 512 stacked 384 x 384
+    inverses (the bench's fused-ratio workload)."""
+    grid, N, coefs, _ = W.make_table(3)
+    s = q.Spline(grid, coefs, "f32")
+    del coefs
+    pos_np = W.make_positions(3)
+    pos = torch.from_numpy(pos_np).cuda()
+    import os
+    s.autotune(pos, reps=2, cache_path=os.path.join(os.path.dirname(q.__file__), "tune_cache.txt"))
+    ainv = torch.from_numpy(W.make_inverse_rows(3, pos_np.shape[0], N)).cuda()
+    st = s.autotune_sorted(pos, reps=1, cache_path=os.path.join(os.path.dirname(q.__file__), "tune_cache.txt"))
+    _say("case sorted ratio full", st)
+    D = s.eval_ratio_vgl_sorted(pos, ainv)
+    _same(torch, (s.eval_ratio_v_sorted(pos, ainv),), (s.eval_ratio_v(pos, ainv),))
+    s.set_tile(st)  # the plain path under the sorted shape
+    _same(torch, (D,), (s.eval_ratio_vgl(pos, ainv),))
