@@ -451,12 +451,16 @@ def main() -> int:
 
     t_vgh = pick_vgh(pos)
     ms_vgh, _ = time_steps(torch, lambda: sh.eval_vgh(pos, out=vgh_out), args.steps, args.warmup)
+    ms_vgh_s, _ = time_steps(torch, lambda: sh.eval_vgh_sorted(pos, out=vgh_out), args.steps, args.warmup)
     sh.set_lattice(hexl)
     t_vgh_hex = pick_vgh(pos_hex)
     ms_vgh_hex, _ = time_steps(torch, lambda: sh.eval_vgh(pos_hex, out=vgh_out), args.steps, args.warmup)
+    ms_vgh_hex_s, _ = time_steps(torch, lambda: sh.eval_vgh_sorted(pos_hex, out=vgh_out), args.steps, args.warmup)
     Vh, Gh, Hh = vgh_out
     Lbuf = torch.empty((B, N), dtype=torch.float32, device=dev)
     ms_vgl_hex, _ = time_steps(torch, lambda: sh.eval_vgl(pos_hex, out=(Vh, Gh, Lbuf)), args.steps, args.warmup)
+    ms_vgl_hex_s, _ = time_steps(torch, lambda: sh.eval_vgl_sorted(pos_hex, out=(Vh, Gh, Lbuf)), args.steps,
+                                 args.warmup)
     hidx = idx[:128]
     hit = torch.from_numpy(hidx).to(dev)
     sh.eval_vgh(pos_hex, out=vgh_out)
@@ -477,7 +481,15 @@ def main() -> int:
         "evals_per_s": units / (ms_vgl_hex * 1e-3), "ms_per_step": ms_vgl_hex, "tile": list(t_vgh_hex),
         "bytes_per_unit": BYTES_PER_UNIT["f32"],
         "hbm_frac": units * BYTES_PER_UNIT["f32"] / (ms_vgl_hex * 1e-3) / 1e9 / PEAK_HBM_GBS}
-    log("bench: vgh %.3f ms, vgh hexagonal %.3f ms, vgl hexagonal %.3f ms" % (ms_vgh, ms_vgh_hex, ms_vgl_hex))
+    forms["f32_vgh_locality_sorted"] = {
+        "ms_per_step": ms_vgh_s, "ms_per_step_hexagonal": ms_vgh_hex_s, "tile": list(t_vgh_hex),
+        "evals_per_s": units / (ms_vgh_s * 1e-3), "evals_per_s_hexagonal": units / (ms_vgh_hex_s * 1e-3),
+        "speedup_vs_f32_vgh": ms_vgh / ms_vgh_s, "speedup_vs_f32_vgh_hexagonal": ms_vgh_hex / ms_vgh_hex_s}
+    forms["f32_vgl_hexagonal_locality_sorted"] = {
+        "ms_per_step": ms_vgl_hex_s, "evals_per_s": units / (ms_vgl_hex_s * 1e-3), "tile": list(t_vgh_hex),
+        "speedup_vs_f32_vgl_hexagonal": ms_vgl_hex / ms_vgl_hex_s}
+    log("bench: vgh %.3f ms, vgh hexagonal %.3f ms, vgl hexagonal %.3f ms; sorted %.3f / %.3f / %.3f ms" % (
+        ms_vgh, ms_vgh_hex, ms_vgl_hex, ms_vgh_s, ms_vgh_hex_s, ms_vgl_hex_s))
 
     # C2 (48^3, N = 192, FP32: a 102 MB table that the 256 MB MALL holds)
     # against the MALL-resident read rate, and one GPU's share of an 8-way

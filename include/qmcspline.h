@@ -146,7 +146,9 @@ int spline_eval_v(const spline_t* s, const double* pos_dev, int64_t B, void* V, 
  *                  spline_sorted_workspace_bytes(s, B) bytes (0 for a NULL
  *                  handle or B outside [0, 2^31)); its contents on entry
  *                  do not matter and are overwritten.
- * Orthorhombic cells only (SPL_EUNSUPPORTED after spline_set_lattice);
+ * For a general cell (after spline_set_lattice) spline_eval_vgl_sorted
+ * sorts by the fractional coordinates and runs the general-cell kernel; the
+ * value-only form is for orthorhombic cells (SPL_EUNSUPPORTED otherwise).
  * SPL_ENOMEM for a short workspace; B == 0 is a no-op.  Asynchronous on
  * `stream`; calls that share a workspace must not overlap. */
 size_t spline_sorted_workspace_bytes(const spline_t* s, int64_t B);
@@ -154,6 +156,10 @@ int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
                            void* workspace_dev, size_t workspace_bytes, void* stream);
 int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
                          size_t workspace_bytes, void* stream);
+/* spline_eval_vgh in locality order (same arguments and results, bit for
+ * bit; the VGH-family tile shape), with the workspace above. */
+int spline_eval_vgh_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* H,
+                           void* workspace_dev, size_t workspace_bytes, void* stream);
 /* The fused determinant ratio in locality order: arguments and errors of
  * spline_eval_ratio_vgl / spline_eval_ratio_v, plus the workspace of
  * spline_eval_vgl_sorted.  Uses the sorted tile shape (the value tile for

@@ -67,6 +67,7 @@ def lib():
             "spline_eval_v_sorted": ([p, p, i64, p, p, sz, p], ctypes.c_int),
             "spline_eval_ratio_vgl_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
             "spline_eval_ratio_v_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
+            "spline_eval_vgh_sorted": ([p, p, i64, p, p, p, p, sz, p], ctypes.c_int),
             "spline_set_sorted_tile": ([p, p], ctypes.c_int),
             "spline_get_sorted_tile": ([p, p], ctypes.c_int),
             "spline_autotune_sorted": ([p, p, i64, p, p, p, p, sz, ctypes.c_int32, ctypes.c_char_p, p, p],
@@ -392,6 +393,22 @@ class Spline:
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_vgh(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()),
                                         ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(H.data_ptr()), sp))
+        return V, G, H
+
+    def eval_vgh_sorted(self, pos, out=None, workspace=None, stream=None):
+        """eval_vgh in locality order (same results bit for bit)."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V, G, H = out if out is not None else self.alloc_vgh(B)
+        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (H, (B, 6, self.norb))):
+            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("output tensor has wrong shape/dtype/device")
+        wp, wn = self._sorted_ws(B, workspace)
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_eval_vgh_sorted(self._h, ctypes.c_void_p(pos.data_ptr()), B,
+                                               ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                               ctypes.c_void_p(H.data_ptr()), wp, wn, sp))
         return V, G, H
 
     def get_value_tile(self):

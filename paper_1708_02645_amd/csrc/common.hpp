@@ -120,6 +120,8 @@ EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, i
 spline_tile default_vgh_tile(const spline_s* s);
 void set_general_args(const spline_s* s, EvalArgs& a);
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
+int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
+                       const int32_t* idx, hipStream_t st);
 int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, void* G, void* H, int32_t reps,
                  hipStream_t st, spline_tile* chosen);
 // Tile validation and the tuning cache (spline_host.cpp).

@@ -31,7 +31,9 @@ constexpr int kLocBits = 5;                            // coarse blocks per dime
 constexpr int kLocBuckets = 1 << (3 * kLocBits);       // Morton keys < 2^15
 
 struct LocKey {
-    double inv[3];    // 1 / cell length
+    double inv[3];    // 1 / cell length (orthorhombic cell)
+    double ilat[9];   // general cell: fractional u_d = sum_c r_c ilat[c*3 + d]
+    int32_t general;
     int32_t n[3];     // grid points per dimension
     int32_t shift;    // coarse block = 2^shift cells per dimension
 };
@@ -62,9 +64,10 @@ __global__ __launch_bounds__(kLocThreads) void loc_key_kernel(const double* pos,
     const int64_t b = (int64_t)blockIdx.x * kLocThreads + threadIdx.x;
     if (b >= B) return;
     uint32_t c[3];
+    const double r[3] = {pos[3 * b], pos[3 * b + 1], pos[3 * b + 2]};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double u = pos[3 * b + d] * k.inv[d];
+        double u = k.general ? r[0] * k.ilat[d] + r[1] * k.ilat[3 + d] + r[2] * k.ilat[6 + d] : r[d] * k.inv[d];
         u -= floor(u);
         int i = (u >= 0.0 && u < 1.0) ? (int)(u * k.n[d]) : 0;
         i = i < 0 ? 0 : (i >= k.n[d] ? k.n[d] - 1 : i);
@@ -160,7 +163,6 @@ static int sorted_check(const spline_s* s, const double* pos, int64_t B, void* V
     if (ws_bytes < loc_bytes(B)) return fail(SPL_ENOMEM, "workspace smaller than spline_sorted_workspace_bytes()");
     int64_t tmp;
     if (!mul_ok(B, (int64_t)s->norb * 3 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
-    if (s->general) return fail(SPL_EUNSUPPORTED, "locality-ordered evaluation is built for orthorhombic cells");
     int dev = -1;
     QS_HIP(hipGetDevice(&dev));
     if (dev != s->device) return fail(SPL_EINVAL, "current HIP device differs from the table's device");
@@ -173,6 +175,8 @@ static int sort_positions(const spline_s* s, const double* pos, int64_t B, int p
                           const int32_t** perm_out)
 {
     LocKey k;
+    k.general = s->general;
+    for (int i = 0; i < 9; ++i) k.ilat[i] = s->ilat[i];
     int bits = 0;
     for (int d = 0; d < 3; ++d) {
         k.inv[d] = 1.0 / s->grid.cell[d];
@@ -212,12 +216,27 @@ static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const d
     return launch(*v, a, st);
 }
 
+// The VGH family in locality order (the Hessian, or the general-cell VGL).
+static int sorted_vgh(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
+                      void* ws, hipStream_t st)
+{
+    const int32_t* perm = nullptr;
+    int rc = sort_positions(s, pos, B, s->htile.pb, ws, st, &perm);
+    if (rc) return rc;
+    return vgh_launch_indexed(s, hessian, pos, B, V, G, H, perm, st);
+}
+
 static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, void* ws,
                          size_t ws_bytes, void* stream, bool vgl)
 {
     int rc = sorted_check(s, pos, B, V, G, L, ws, ws_bytes, vgl);
     if (rc || B == 0) return rc;
-    return sorted_run(s, vgl ? s->stile : s->vtile, vgl, pos, B, V, G, L, ws, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->general) {
+        if (!vgl) return fail(SPL_EUNSUPPORTED, "value-only evaluation is built for orthorhombic cells");
+        return sorted_vgh(s, false, pos, B, V, G, L, ws, st);
+    }
+    return sorted_run(s, vgl ? s->stile : s->vtile, vgl, pos, B, V, G, L, ws, st);
 }
 
 }  // namespace qs
@@ -257,6 +276,7 @@ static int sorted_ratio(const spline_s* s, const double* pos, int64_t B, const v
     if (ld < 0) return fail(SPL_EINVAL, "ld must be >= 0");
     int rc = sorted_check(s, pos, B, D, D, D, ws, ws_bytes, false);
     if (rc || B == 0) return rc;
+    if (s->general) return fail(SPL_EUNSUPPORTED, "the fused ratio is built for orthorhombic cells");
     if (!ainv) return fail(SPL_EINVAL, "NULL inverse-row pointer");
     const uintptr_t eb = s->store == SPL_F64 ? 8 : 4;
     if ((uintptr_t)ainv % eb || (uintptr_t)D % eb)
@@ -293,6 +313,16 @@ int spline_eval_ratio_v_sorted(const spline_t* s, const double* pos_dev, int64_t
     return sorted_ratio(s, pos_dev, B, ainv_dev, ld, rows_dev, R, workspace_dev, workspace_bytes, stream, false);
 }
 
+int spline_eval_vgh_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* H,
+                           void* workspace_dev, size_t workspace_bytes, void* stream)
+{
+    int rc = sorted_check(s, pos_dev, B, V, G, H, workspace_dev, workspace_bytes, true);
+    if (rc || B == 0) return rc;
+    int64_t tmp;
+    if (!mul_ok(B, (int64_t)s->norb * 6 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
+    return sorted_vgh(s, true, pos_dev, B, V, G, H, workspace_dev, static_cast<hipStream_t>(stream));
+}
+
 int spline_set_sorted_tile(spline_t* s, const spline_tile* tile)
 {
     if (!s) return fail(SPL_EINVAL, "handle is NULL");
@@ -319,6 +349,7 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
     int rc = sorted_check(s, pos_dev, B, V, G, L, workspace_dev, workspace_bytes, true);
     if (rc) return rc;
     if (B == 0) return fail(SPL_EINVAL, "autotune needs a non-empty batch");
+    if (s->general) return fail(SPL_EUNSUPPORTED, "general cells use the VGH-family tile (spline_autotune_vgh)");
     if (reps < 1) reps = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const std::string key = tune_key(s, B) + " sorted";

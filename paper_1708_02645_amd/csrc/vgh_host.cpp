@@ -154,7 +154,7 @@ static VghArgs make_vgh_args(const spline_s* s, const spline_tile& t, const doub
 }
 
 static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const double* pos, int64_t B, void* V,
-                      void* G, void* H, hipStream_t st)
+                      void* G, void* H, hipStream_t st, const int32_t* idx = nullptr)
 {
     const VghVariant* v = find_vgh(s->store, t, out);
     if (!v || !vgh_fits(s, *v)) return fail(SPL_EUNSUPPORTED, "tile shape not compiled for the VGH kernels");
@@ -165,6 +165,7 @@ static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const do
     const int64_t blocks = (B + t.pb - 1) / t.pb;
     if (blocks > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "batch too large for one launch");
     VghArgs va = make_vgh_args(s, t, pos, B, V, G, H);
+    va.e.idx = idx;
     void* params[] = {&va};
     QS_HIP(hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(kBlock), params, v->lds_per_pos * (size_t)t.pb, st));
     QS_HIP(hipGetLastError());
@@ -175,6 +176,14 @@ static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const do
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st)
 {
     return vgh_launch(s, s->htile, VGH_OUT_L, pos, B, V, G, L, st);
+}
+
+// The VGH family (Hessian, or the general-cell Laplacian) through an index
+// list, with the handle's VGH-family tile (locality-ordered evaluation).
+int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
+                       const int32_t* idx, hipStream_t st)
+{
+    return vgh_launch(s, s->htile, hessian ? VGH_OUT_H : VGH_OUT_L, pos, B, V, G, H, st, idx);
 }
 
 static int check_outputs(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* H)

@@ -99,7 +99,39 @@ def test_edges(torch, q):
     assert L.spline_sorted_workspace_bytes(s._h, 10) % 256 == 0
     s.set_lattice([[1.3, 0, 0], [0.2, 0.7, 0], [0, 0, 2.1]])
     with pytest.raises(q.SplineError):
-        s.eval_vgl_sorted(pos)
+        s.eval_v_sorted(pos)  # value only: orthorhombic cells
+    with pytest.raises(q.SplineError):
+        s.eval_ratio_vgl_sorted(pos, torch.zeros((64, 40), dtype=torch.float32, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vgh_and_general_cells_equal(torch, q, oracle, dtype):
+    """VGH (orthorhombic and a triclinic cell) and the general-cell VGL in
+    locality order equal the plain entry points bit for bit; the triclinic
+    VGH is also checked against the FP64 oracle."""
+    rng = np.random.default_rng(13)
+    grid = (10, 12, 9)
+    coefs = rng.uniform(-1, 1, grid + (48,))
+    s = q.Spline(grid, coefs, dtype)
+    lat = np.array([[1.0, 0.0, 0.0], [0.3, 0.9, 0.0], [-0.2, 0.1, 1.2]])
+    for general in (False, True):
+        if general:
+            s.set_lattice(lat)
+        for B in (1, 700, 3001):
+            _say("case sorted vgh", dtype, general, B)
+            pos_np = rng.uniform(-2, 2, (B, 3))
+            pos = torch.from_numpy(pos_np).cuda()
+            ref = s.eval_vgh(pos)
+            got = s.eval_vgh_sorted(pos)
+            _same(torch, got, ref)
+            if general:
+                _same(torch, s.eval_vgl_sorted(pos), s.eval_vgl(pos))
+    deq = coefs if dtype == "f64" else oracle.dequantize(coefs, dtype)[0]
+    ref = oracle.eval_vgh(grid, deq, pos_np[:200], lat)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for name, a, b in zip(("V", "G", "H"), got, ref):
+        e = oracle.rel_err(a[:200].cpu().numpy(), b)
+        assert e <= tol, "%s %s: %.3e" % (dtype, name, e)
 
 
 def test_tiles_and_chunk_dealing(torch, q):
