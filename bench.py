@@ -588,14 +588,32 @@ def main() -> int:
 
         ms_sep, _ = time_steps(torch, separate, args.steps, args.warmup)
         info = plan.info()
+        # the same plan in locality order (positions sorted on the device in
+        # every launch, the task list dealt to the XCDs in eight segments)
+        outs_plain = [[t.clone() for t in o] for o in plan.outs]
+        plan_s = q.Plan(sp, ps, outs=plan.outs, tune_reps=3, sorted=True)
+        ms_plan_s, _ = time_steps(torch, plan_s.launch, args.steps, args.warmup)
+        plan.launch()
+        same_s = True
+        plan_s.launch()
+        torch.cuda.synchronize()
+        for o, e in zip(plan_s.outs, outs_plain):
+            same_s = same_s and all(bool(torch.equal(a, b)) for a, b in zip(o, e))
+        info_s = plan_s.info()
+        del outs_plain
         forms["ragged_4_tables_f32"] = {
             "positions": [int(p.shape[0]) for p in ps], "norb": [s.norb for s in sp],
             "evals_per_s": units_r / (ms_plan * 1e-3), "ms_per_launch": ms_plan,
             "ms_four_separate_launches": ms_sep, "speedup_vs_separate": ms_sep / ms_plan,
             "hbm_frac": units_r * BYTES_PER_UNIT["f32"] / (ms_plan * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "tile": list(info["tile"]), "tasks": info["tasks"], "persistent_workgroups": info["blocks"]}
-        log("bench: ragged plan %.3f ms vs separate %.3f ms" % (ms_plan, ms_sep))
-        del plan, sp, ps
+        forms["ragged_4_tables_f32_locality_sorted"] = {
+            "evals_per_s": units_r / (ms_plan_s * 1e-3), "ms_per_launch": ms_plan_s,
+            "speedup_vs_plan": ms_plan / ms_plan_s, "bitwise_equal_to_plan": same_s,
+            "tile": list(info_s["tile"]), "tasks": info_s["tasks"], "persistent_workgroups": info_s["blocks"]}
+        log("bench: ragged plan %.3f ms (sorted %.3f ms, equal %s) vs separate %.3f ms" % (
+            ms_plan, ms_plan_s, same_s, ms_sep))
+        del plan, plan_s, sp, ps
         torch.cuda.empty_cache()
 
     if args.mlp_steps > 0:

@@ -374,6 +374,20 @@ int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
                        void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
                        spline_plan_t** out);
 
+/* A plan whose every launch first sorts each table's positions on the
+ * device into locality order (as spline_eval_vgl_sorted) and then deals
+ * the task list to the XCDs in eight contiguous segments (workgroups steal
+ * from the other segments once theirs is exhausted), so tasks that share
+ * table rows share an L2.  Same arguments and outputs as spline_plan_create
+ * (bit for bit); the workspace also holds each table's sort scratch:
+ * spline_plan_workspace_bytes_sorted() bytes (0 on invalid input or a
+ * table with 2^31 or more positions). */
+size_t spline_plan_workspace_bytes_sorted(int32_t n_tabs, const int64_t* B_per_tab);
+int spline_plan_create_sorted(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+                              const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
+                              void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
+                              spline_plan_t** out);
+
 /* One replay of the captured graph on `stream` (asynchronous). */
 int spline_plan_launch(const spline_plan_t* plan, void* stream);
 

@@ -104,7 +104,9 @@ def lib():
             "spline_destroy": ([p], ctypes.c_int),
             "spline_last_error": ([], ctypes.c_char_p),
             "spline_plan_workspace_bytes": ([i32, p], sz),
+            "spline_plan_workspace_bytes_sorted": ([i32, p], sz),
             "spline_plan_create": ([p, i32, p, p, p, p, p, p, sz, i32, p, p], ctypes.c_int),
+            "spline_plan_create_sorted": ([p, i32, p, p, p, p, p, p, sz, i32, p, p], ctypes.c_int),
             "spline_plan_launch": ([p, p], ctypes.c_int),
             "spline_plan_launch_eager": ([p, p], ctypes.c_int),
             "spline_plan_get_info": ([p, p, p, p], ctypes.c_int),
@@ -544,10 +546,11 @@ class Plan:
     float64 [B_t, 3] device tensors (B_t may be 0).  Outputs are allocated
     here (or passed as a list of (V, G, L)) and stay bound to the plan."""
 
-    def __init__(self, splines, positions, outs=None, tune_reps: int = 3, stream=None):
+    def __init__(self, splines, positions, outs=None, tune_reps: int = 3, stream=None, sorted=False):
         import torch
 
         self._torch = torch
+        self.sorted = bool(sorted)
         n = len(splines)
         if n == 0 or len(positions) != n:
             raise ValueError("need one positions tensor per table")
@@ -556,7 +559,7 @@ class Plan:
         self.outs = list(outs) if outs is not None else [s.alloc_outputs(p.shape[0]) for s, p in zip(splines, positions)]
         dev = splines[0].device
         Bs = (ctypes.c_int64 * n)(*[p.shape[0] for p in self.positions])
-        nb = int(lib().spline_plan_workspace_bytes(n, Bs))
+        nb = int((lib().spline_plan_workspace_bytes_sorted if self.sorted else lib().spline_plan_workspace_bytes)(n, Bs))
         if nb == 0:
             check(-1)
         self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -570,8 +573,8 @@ class Plan:
         L_ = lib()
         with torch.cuda.device(dev):
             sp, _ = _stream_ptr(torch, dev, stream)
-            check(L_.spline_plan_create(tabs, n, Bs, pos, V, G, L, vp(self.ws.data_ptr()), nb, int(tune_reps), sp,
-                                        ctypes.byref(h)))
+            create = L_.spline_plan_create_sorted if self.sorted else L_.spline_plan_create
+            check(create(tabs, n, Bs, pos, V, G, L, vp(self.ws.data_ptr()), nb, int(tune_reps), sp, ctypes.byref(h)))
         self._h = h
         self.device = dev
 

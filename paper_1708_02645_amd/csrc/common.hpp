@@ -71,9 +71,11 @@ struct PlanTask {
 struct PlanArgs {
     const EvalArgs* tabs;   // device, one per table
     const PlanTask* tasks;  // device, ntasks entries, processed in order of popping
-    unsigned int* counter;  // device work counter, zero at launch
+    unsigned int* counter;  // device work counters (one per segment), zero at launch
     int32_t ntasks;
+    int32_t nseg;           // 1, or 8: the task list in eight contiguous segments, one per XCD
 };
+constexpr int kPlanSegs = 8;
 
 // One compiled kernel variant.
 struct Variant {
@@ -122,6 +124,13 @@ void set_general_args(const spline_s* s, EvalArgs& a);
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
 int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
                        const int32_t* idx, hipStream_t st);
+// Locality ordering (locality.hip): workspace bytes for B positions, and the
+// device sort of B positions into an index list for workgroups of pb
+// positions (pb <= 0: plain sorted order).
+size_t loc_bytes(int64_t B);
+const int32_t* loc_perm(const void* ws, int64_t B);  // where sort_positions leaves the index list
+int sort_positions(const spline_s* s, const double* pos, int64_t B, int pb, void* ws, hipStream_t st,
+                   const int32_t** perm_out);
 int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, void* G, void* H, int32_t reps,
                  hipStream_t st, spline_tile* chosen);
 // Tile validation and the tuning cache (spline_host.cpp).

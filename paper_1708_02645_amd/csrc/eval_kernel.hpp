@@ -530,9 +530,14 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalArgs a)
 }
 
 // Several tables in one launch (ragged batches): a persistent grid pops
-// tasks (table, first position, count <= pb) from a device counter until the
-// list is exhausted.  Every workgroup exits once the counter passes ntasks,
-// so the grid always drains.  The counter must be zero at launch
+// tasks (table, first position, count <= pb) from device counters until the
+// list is exhausted.  With nseg = 8 the list is cut into eight contiguous
+// segments and workgroup i starts on segment i mod 8 (workgroups are
+// dispatched to the eight XCDs in turn), so tasks that are neighbours in the
+// list (in a locality-ordered plan: positions sharing table rows) run on one
+// XCD and share its L2; a workgroup whose segment is exhausted moves on to
+// the next one.  Every workgroup exits once it has found all nseg segments
+// exhausted, so the grid always drains.  The counters must be zero at launch
 // (plan_reset_kernel, captured in the same graph).
 template <spline_dtype S, int CW, int NCH, int LPP>
 __global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs pa)
@@ -541,15 +546,22 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs pa)
     extern __shared__ unsigned char lds_raw[];
     PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
     __shared__ int s_task;
-    for (;;) {
-        if (threadIdx.x == 0) s_task = (int)atomicAdd(pa.counter, 1u);
-        __syncthreads();
-        const int t = uniform<int>(s_task);
-        if (t >= pa.ntasks) break;  // uniform across the workgroup
-        const PlanTask tk = pa.tasks[t];
-        const EvalArgs a = pa.tabs[tk.table];
-        eval_block<S, CW, NCH, LPP, true>(a, tk.first, tk.count, W);
-        __syncthreads();  // W and s_task are rewritten by the next task
+    const int home = (int)(blockIdx.x % (unsigned)pa.nseg);
+    for (int k = 0; k < pa.nseg; ++k) {
+        const int seg = (home + k) % pa.nseg;
+        const int t0 = (int)((int64_t)pa.ntasks * seg / pa.nseg);
+        const int t1 = (int)((int64_t)pa.ntasks * (seg + 1) / pa.nseg);
+        for (;;) {
+            if (threadIdx.x == 0) s_task = t0 + (int)atomicAdd(pa.counter + seg, 1u);
+            __syncthreads();
+            const int t = uniform<int>(s_task);
+            __syncthreads();  // every thread has read s_task before it can be rewritten
+            if (t >= t1) break;  // uniform across the workgroup
+            const PlanTask tk = pa.tasks[t];
+            const EvalArgs a = pa.tabs[tk.table];
+            eval_block<S, CW, NCH, LPP, true>(a, tk.first, tk.count, W);
+            __syncthreads();  // W is rewritten by the next task
+        }
     }
 }
 

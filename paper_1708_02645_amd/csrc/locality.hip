@@ -124,9 +124,9 @@ __global__ __launch_bounds__(kLocThreads) void loc_scatter_kernel(int64_t B, int
     const int64_t b = (int64_t)blockIdx.x * kLocThreads + threadIdx.x;
     if (b >= B) return;
     const int64_t j = (int64_t)offset[key[b]] + rank[b];
-    const int64_t full = B / pb, c = j / pb, r = j - c * pb;
     int64_t dst = j;
-    if (c < full) {
+    const int64_t full = pb > 0 ? B / pb : 0, c = pb > 0 ? j / pb : 0, r = j - c * pb;
+    if (c < full) {  // pb <= 0: plain sorted order (the caller deals the work)
         const int64_t c8 = full / 8, rem = full % 8, big = rem * (c8 + 1);  // XCDs x < rem take c8 + 1 chunks
         int64_t x, k;
         if (c < big) {
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kLocThreads) void loc_scatter_kernel(int64_t B, int
 static_assert(kLocBuckets % kLocScanThreads == 0, "scan runs must tile the buckets");
 
 // Workspace: count [kLocBuckets], key [B], rank [B], perm [B], int32 each.
-static size_t loc_bytes(int64_t B)
+size_t loc_bytes(int64_t B)
 {
     const size_t words = (size_t)kLocBuckets + 3 * (size_t)B;
     return (words * 4 + 255) & ~(size_t)255;
@@ -169,9 +169,11 @@ static int sorted_check(const spline_s* s, const double* pos, int64_t B, void* V
     return SPL_OK;
 }
 
-// The sort (four small launches) for workgroups of pb positions; returns
-// the index list inside the workspace.
-static int sort_positions(const spline_s* s, const double* pos, int64_t B, int pb, void* ws, hipStream_t st,
+const int32_t* loc_perm(const void* ws, int64_t B) { return static_cast<const int32_t*>(ws) + kLocBuckets + 2 * B; }
+
+// The sort (four small launches) for workgroups of pb positions (pb <= 0:
+// no dealing to XCDs); returns the index list inside the workspace.
+int sort_positions(const spline_s* s, const double* pos, int64_t B, int pb, void* ws, hipStream_t st,
                           const int32_t** perm_out)
 {
     LocKey k;

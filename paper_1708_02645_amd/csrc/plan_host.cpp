@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -14,11 +15,11 @@
 
 namespace qs {
 
-// Zeroes the work counter of a plan (a kernel, not a memset node, so that the
-// captured graph holds only kernel nodes).
+// Zeroes the work counters of a plan (a kernel, not a memset node, so that
+// the captured graph holds only kernel nodes).
 __global__ void plan_reset_kernel(unsigned int* counter)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+    if (threadIdx.x < kPlanSegs && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 constexpr int kMinPb = 16;  // smallest positions-per-task; sizes the workspace
@@ -27,20 +28,28 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct WsLayout {
     size_t counter, tabs, tasks, total;
+    std::vector<size_t> loc;  // locality-ordered plans: each table's sort workspace
 };
 
-static bool ws_layout(int32_t n_tabs, const int64_t* B, WsLayout* w, int64_t* max_tasks)
+static bool ws_layout(int32_t n_tabs, const int64_t* B, bool sorted, WsLayout* w, int64_t* max_tasks)
 {
     int64_t nt = 0;
     for (int32_t t = 0; t < n_tabs; ++t) {
         if (B[t] < 0) return false;
+        if (sorted && B[t] > (int64_t)std::numeric_limits<int32_t>::max()) return false;
         nt += (B[t] + kMinPb - 1) / kMinPb;
         if (nt > (int64_t)1 << 30) return false;
     }
-    w->counter = 0;
+    w->counter = 0;  // kPlanSegs counters in the first 256 bytes
     w->tabs = 256;
     w->tasks = w->tabs + align256((size_t)n_tabs * sizeof(EvalArgs));
     w->total = w->tasks + align256((size_t)std::max<int64_t>(nt, 1) * sizeof(PlanTask));
+    w->loc.clear();
+    if (sorted)
+        for (int32_t t = 0; t < n_tabs; ++t) {
+            w->loc.push_back(w->total);
+            w->total += loc_bytes(B[t]);
+        }
     *max_tasks = nt;
     return true;
 }
@@ -58,6 +67,8 @@ struct spline_plan_s {
     const qs::Variant* var = nullptr;
     int32_t ntasks = 0;
     int32_t nblocks = 0;
+    bool sorted = false;              // positions sorted on the device before each launch
+    std::vector<const int32_t*> perm; // locality-ordered plans: each table's index list
     int device = -1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -87,6 +98,7 @@ static int stage_config(spline_plan_s* p, const Variant* v, const spline_tile& t
     std::vector<EvalArgs> args(p->tabs.size());
     for (size_t i = 0; i < p->tabs.size(); ++i) {
         args[i] = make_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
+        if (p->sorted) args[i].idx = p->perm[i];
     }
     std::vector<PlanTask> tasks = make_tasks(p, t.pb);
     QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(EvalArgs),
@@ -111,11 +123,19 @@ static int stage_config(spline_plan_s* p, const Variant* v, const spline_tile& t
 static int launch_plan(const spline_plan_s* p, hipStream_t st)
 {
     if (p->ntasks == 0) return SPL_OK;
+    if (p->sorted)  // each table's positions in locality order; the queue's segments deal them to the XCDs
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            if (p->B[i] == 0) continue;
+            const int32_t* perm = nullptr;
+            const int rc = sort_positions(p->tabs[i], p->pos[i], p->B[i], 0, p->ws + p->lay.loc[i], st, &perm);
+            if (rc) return rc;
+        }
     unsigned int* counter = reinterpret_cast<unsigned int*>(p->ws + p->lay.counter);
     hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, st, counter);
     QS_HIP(hipGetLastError());
     PlanArgs pa{reinterpret_cast<const EvalArgs*>(p->ws + p->lay.tabs),
-                reinterpret_cast<const PlanTask*>(p->ws + p->lay.tasks), counter, p->ntasks};
+                reinterpret_cast<const PlanTask*>(p->ws + p->lay.tasks), counter, p->ntasks,
+                p->sorted ? kPlanSegs : 1};
     void* params[] = {&pa};
     const size_t lds = p->var->lds_per_pos * (size_t)p->tile.pb;
     QS_HIP(hipLaunchKernel(p->var->plan_fn, dim3(p->nblocks), dim3(kBlock), params, lds, st));
@@ -156,19 +176,21 @@ using namespace qs;
 
 extern "C" {
 
-size_t spline_plan_workspace_bytes(int32_t n_tabs, const int64_t* B_per_tab)
+}  // extern "C"
+
+static size_t plan_ws_bytes(int32_t n_tabs, const int64_t* B_per_tab, bool sorted)
 {
     if (n_tabs <= 0 || !B_per_tab) return 0;
     WsLayout w;
     int64_t nt = 0;
-    if (!ws_layout(n_tabs, B_per_tab, &w, &nt)) return 0;
+    if (!ws_layout(n_tabs, B_per_tab, sorted, &w, &nt)) return 0;
     return w.total;
 }
 
-int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
                        const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
                        void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
-                       spline_plan_t** out)
+                       spline_plan_t** out, bool sorted)
 {
     if (!out) return fail(SPL_EINVAL, "out is NULL");
     *out = nullptr;
@@ -179,7 +201,7 @@ int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
         return fail(SPL_EINVAL, "workspace not 256-byte aligned");
     WsLayout lay;
     int64_t max_tasks = 0;
-    if (!ws_layout(n_tabs, B_per_tab, &lay, &max_tasks)) return fail(SPL_EINVAL, "negative or huge batch size");
+    if (!ws_layout(n_tabs, B_per_tab, sorted, &lay, &max_tasks)) return fail(SPL_EINVAL, "negative or huge batch size");
     if (workspace_bytes < lay.total) return fail(SPL_ENOMEM, "workspace smaller than spline_plan_workspace_bytes()");
     int dev = -1;
     QS_HIP(hipGetDevice(&dev));
@@ -204,6 +226,10 @@ int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     p->ws = static_cast<unsigned char*>(workspace_dev);
     p->lay = lay;
     p->device = dev;
+    p->sorted = sorted;
+    if (sorted)  // the index lists sit at fixed places in each table's sort workspace
+        for (int32_t t = 0; t < n_tabs; ++t)
+            p->perm.push_back(loc_perm(p->ws + lay.loc[t], B_per_tab[t]));
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     // Candidate shapes: tiles that divide every table's row, times pb.
@@ -311,6 +337,36 @@ int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     }
     *out = p;
     return SPL_OK;
+}
+
+extern "C" {
+
+size_t spline_plan_workspace_bytes(int32_t n_tabs, const int64_t* B_per_tab)
+{
+    return plan_ws_bytes(n_tabs, B_per_tab, false);
+}
+
+size_t spline_plan_workspace_bytes_sorted(int32_t n_tabs, const int64_t* B_per_tab)
+{
+    return plan_ws_bytes(n_tabs, B_per_tab, true);
+}
+
+int spline_plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+                       const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
+                       void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
+                       spline_plan_t** out)
+{
+    return plan_create(tabs, n_tabs, B_per_tab, pos_dev, V, G, L, workspace_dev, workspace_bytes, tune_reps, stream,
+                       out, false);
+}
+
+int spline_plan_create_sorted(const spline_t* const* tabs, int32_t n_tabs, const int64_t* B_per_tab,
+                              const double* const* pos_dev, void* const* V, void* const* G, void* const* L,
+                              void* workspace_dev, size_t workspace_bytes, int32_t tune_reps, void* stream,
+                              spline_plan_t** out)
+{
+    return plan_create(tabs, n_tabs, B_per_tab, pos_dev, V, G, L, workspace_dev, workspace_bytes, tune_reps, stream,
+                       out, true);
 }
 
 int spline_plan_launch(const spline_plan_t* p, void* stream)

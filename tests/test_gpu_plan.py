@@ -54,11 +54,14 @@ def _same(a, b):
 SPECS = [((8, 8, 8), 64, 1000), ((10, 9, 8), 128, 257), ((12, 12, 12), 256, 1), ((9, 7, 11), 384, 700)]
 
 
+@pytest.mark.parametrize("sorted_", [False, True])
 @pytest.mark.parametrize("tune", [0, 2])
-def test_plan_equals_single_table_bitwise(torch, q, oracle, tune):
+def test_plan_equals_single_table_bitwise(torch, q, oracle, tune, sorted_):
+    """Plain plans (one work queue) and locality-ordered plans (positions
+    sorted on the device at each launch, the queue in eight segments)."""
     sp, pos, coefs = _tables(q, torch, SPECS, 11)
-    _say("case plan tune", tune)
-    plan = q.Plan(sp, pos, tune_reps=tune)
+    _say("case plan tune", tune, "sorted", sorted_)
+    plan = q.Plan(sp, pos, tune_reps=tune, sorted=sorted_)
     info = plan.info()
     _say("plan info", info)
     assert info["tasks"] > 0 and info["blocks"] >= 1
@@ -76,9 +79,10 @@ def test_plan_equals_single_table_bitwise(torch, q, oracle, tune):
             assert oracle.rel_err(g_[:k].cpu().numpy(), r_) <= 1e-5
 
 
-def test_plan_graph_replays_match_eager(torch, q):
+@pytest.mark.parametrize("sorted_", [False, True])
+def test_plan_graph_replays_match_eager(torch, q, sorted_):
     sp, pos, _ = _tables(q, torch, SPECS, 12)
-    plan = q.Plan(sp, pos, tune_reps=0)
+    plan = q.Plan(sp, pos, tune_reps=0, sorted=sorted_)
     plan.launch_eager()
     torch.cuda.synchronize()
     eager = [[t.clone() for t in o] for o in plan.outs]
@@ -98,10 +102,12 @@ def test_plan_graph_replays_match_eager(torch, q):
         del x
 
 
-def test_plan_moving_positions(torch, q):
-    """Positions may change between launches (same buffers)."""
+@pytest.mark.parametrize("sorted_", [False, True])
+def test_plan_moving_positions(torch, q, sorted_):
+    """Positions may change between launches (same buffers); a locality-
+    ordered plan sorts them again at every launch."""
     sp, pos, _ = _tables(q, torch, SPECS[:2], 13)
-    plan = q.Plan(sp, pos, tune_reps=0)
+    plan = q.Plan(sp, pos, tune_reps=0, sorted=sorted_)
     for rep in range(3):
         _say("case plan move", rep)
         for p in plan.positions:
@@ -112,15 +118,16 @@ def test_plan_moving_positions(torch, q):
             _same(o, s.eval_vgl(p))
 
 
-def test_plan_empty_tables(torch, q):
+@pytest.mark.parametrize("sorted_", [False, True])
+def test_plan_empty_tables(torch, q, sorted_):
     specs = [((8, 8, 8), 64, 0), ((9, 9, 9), 128, 33), ((8, 8, 8), 64, 0)]
     sp, pos, _ = _tables(q, torch, specs, 14)
-    plan = q.Plan(sp, pos, tune_reps=1)
+    plan = q.Plan(sp, pos, tune_reps=1, sorted=sorted_)
     outs = plan.launch()
     torch.cuda.synchronize()
     _same(outs[1], sp[1].eval_vgl(pos[1]))
     sp0, pos0, _ = _tables(q, torch, [((8, 8, 8), 64, 0)], 15)
-    plan0 = q.Plan(sp0, pos0, tune_reps=1)
+    plan0 = q.Plan(sp0, pos0, tune_reps=1, sorted=sorted_)
     assert plan0.info()["tasks"] == 0
     plan0.launch()
     torch.cuda.synchronize()
