@@ -678,6 +678,11 @@ def main() -> int:
                      "attainable_stream_read_GBs": best_read,
                      "frac_of_attainable": achieved / best_read if best_read > 0 else None},
         "cpu_baseline": cpu,
+        "fastest_form": {"form": "f32_locality_sorted", "evals_per_s": forms["f32_locality_sorted"]["evals_per_s"],
+                         "ms_per_step": forms["f32_locality_sorted"]["ms_per_step"],
+                         "note": "the same FP32 batch and outputs (bit for bit) with positions put in locality "
+                                 "order on the device inside the timed step; value and roofline above are the "
+                                 "plain evaluation, whose bound is HBM at the algorithmic bytes"},
         "forms": forms,
         "wall_s_timed": wall32,
     }

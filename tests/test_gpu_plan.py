@@ -174,3 +174,12 @@ def test_c4_ragged_workload(torch, q, oracle):
         errs = [oracle.rel_err(a[idx].cpu().numpy(), b) for a, b in zip(o, r)]
         _say("c4", t["grid"], "eps V/G/L = %.2e %.2e %.2e" % tuple(errs))
         assert max(errs) <= 1e-5
+    # the locality-ordered plan over the same workload: whole outputs equal
+    plain = [[x.clone() for x in o] for o in outs]
+    plan_s = q.Plan(sp, pos, tune_reps=2, sorted=True)
+    _say("c4 sorted plan", plan_s.info())
+    outs_s = plan_s.launch()
+    torch.cuda.synchronize()
+    for o, e in zip(outs_s, plain):
+        for a, b in zip(o, e):
+            assert torch.equal(a, b)

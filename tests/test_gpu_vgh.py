@@ -169,6 +169,14 @@ def test_c3_hexagonal_full_batch_sampled(torch, q, oracle, c3):
     got = _np((V[it], G[it], H[it]))
     _check(oracle, got, oracle.eval_vgh(grid, coefs, pos[idx], HEX), TOL["f32"],
            "vgh c3 hexagonal tile %s" % (s.get_vgh_tile(),))
+    # locality order: the whole batch equal bit for bit (VGH and the general-cell VGL)
+    plain = [t.clone() for t in (V, G, H)]
+    Vs, Gs, Hs = s.eval_vgh_sorted(pd, out=out)
+    for a, b in zip((Vs, Gs, Hs), plain):
+        assert torch.equal(a, b)
+    del plain, out
+    for a, b in zip(s.eval_vgl_sorted(pd), s.eval_vgl(pd)):
+        assert torch.equal(a, b)
 
 
 def test_edges_and_unsupported(torch, q, oracle):
