@@ -81,6 +81,7 @@ def time_steps(torch, fn, steps: int, warmup: int):
 
 
 MLP_FLOP_PER_POS = 2 * 5 * (96 * 256 + 256 * 256 + 256 * 192)
+PEAK_FP32_VECTOR_TFLOPS = 78.6  # unpacked FMA (packed FP32 is not used)
 PEAK_BF16_TFLOPS = 2500.0
 
 
@@ -404,6 +405,8 @@ def main() -> int:
                  "speedup_vs_f32": ms32 / ms_sorted, "bitwise_equal_to_f32": same32,
                  "algorithmic_GBs": units * BYTES_PER_UNIT["f32"] / (ms_sorted * 1e-3) / 1e9,
                  "traffic": traffic_from_profiles(stile32, "vgl_sorted_f32_80cube_n384"),
+                 "fma_floor_ms": units * 320 * 2 / (PEAK_FP32_VECTOR_TFLOPS * 1e12) * 1e3,
+                 "fma_frac_of_fp32_vector_peak": units * 320 * 2 / (ms_sorted * 1e-3) / (PEAK_FP32_VECTOR_TFLOPS * 1e12),
                  "note": "same batch and outputs; positions bucketed by Morton-ordered 4^3-cell blocks on the "
                          "device (4 small launches, timed) and dealt so each XCD takes a contiguous stretch, so "
                          "table rows are re-read from L2 / Infinity Cache: the algorithmic bytes exceed what "
