@@ -8,7 +8,8 @@
 - training lowers the loss; the error map routes; routed positions equal the
   spline bit for bit and the others equal the network bit for bit; routing
   everything reproduces the spline exactly;
-- a saved state resumes with identical outputs.
+- a saved state resumes with identical outputs;
+- what the trained network gains over the table: footprint and speed.
 """
 import sys
 
@@ -150,3 +151,55 @@ def test_training_error_map_fallback_and_resume(torch, q, oracle, small_table):
         np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
     net2.train_step(pos[:4096], spl.eval_vgl(pos[:4096]), lr=1e-4)
     assert net2.info()["step"] == 301
+
+
+def test_surrogate_gain_over_the_table(torch, q, oracle):
+    """What the trained network gains over the method without it, on the
+    48^3 / N=192 table and its 256 x 192 batch: a footprint hundreds of times
+    smaller than the table, and a faster evaluation of the batch (network
+    only, median of timed launches), at an error against the spline that is
+    measured and reported (it does not meet 1e-3: see the error map and the
+    fallback test above)."""
+    grid, N, coefs, _ = W.make_table(5)
+    spl = q.Spline(grid, coefs, "f32")
+    _, Ws, bs = W.mlp_init(5)
+    net = q.SurrogateMLP(N, q.spectral_frequencies(coefs), q.flatten_mlp_params(Ws, bs))
+    train = torch.from_numpy(W.mlp_samples(5, count=4096 * 50)).cuda()
+    net.init_output(spl.eval_vgl(train[:4096]))
+    hv = torch.from_numpy(W.mlp_samples(5, count=20000, validation=True)).cuda()
+    ref = [t.cpu().numpy() for t in spl.eval_vgl(hv)]
+    e0 = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip(net.forward(hv), ref)]
+    for step in range(400):
+        pos = train[(step % 50) * 4096:(step % 50 + 1) * 4096]
+        net.train_step(pos, spl.eval_vgl(pos), lr=5e-3 * 0.5 * (1 + np.cos(np.pi * step / 400)) + 1e-5)
+    e1 = [oracle.rel_err(a.cpu().numpy(), b) for a, b in zip(net.forward(hv), ref)]
+    table_bytes = spl.layout.total_bytes
+    net_bytes = net.layout.n_params * 2
+    _say("surrogate: table %.1f MB, network %.0f KB (%.0fx); eps V/G/L untrained %.3g %.3g %.3g, trained %.3g %.3g %.3g"
+         % ((table_bytes / 1e6, net_bytes / 1e3, table_bytes / net_bytes) + tuple(e0) + tuple(e1)))
+    assert table_bytes > 300 * net_bytes
+    assert all(b < a for a, b in zip(e0, e1))  # training moved every quantity toward the table
+
+    pos = torch.from_numpy(W.make_positions(5)).cuda()
+    out = net._out(pos.shape[0])
+    sout = spl.alloc_outputs(pos.shape[0])
+    spl.autotune(pos, reps=2, out=sout)
+
+    def median_ms(fn, n=15):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(n):
+            e0_, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0_.record()
+            fn()
+            e1_.record()
+            torch.cuda.synchronize()
+            ts.append(e0_.elapsed_time(e1_))
+        return float(np.median(ts))
+
+    ms_net = median_ms(lambda: net.forward(pos, out=out))
+    ms_spl = median_ms(lambda: spl.eval_vgl(pos, out=sout))
+    _say("surrogate: network %.3f ms vs spline %.3f ms on %d positions (%.2fx)" % (ms_net, ms_spl, pos.shape[0],
+                                                                                  ms_spl / ms_net))
+    assert ms_net * 1.3 < ms_spl
