@@ -350,7 +350,26 @@ def main() -> int:
     with torch.cuda.graph(g_dlu):
         dlu_batch()
     ms_dlu_graph, _ = time_steps(torch, g_dlu.replay, max(3, args.steps // 5), 1)
-    del dl, g_dlu
+
+    # the same 16 moves with each accept fused into the next move's ratio
+    def dlu_batch_fused():
+        dl.ratio(inv_d, ks_d[0], phi_d, out=r_d)
+        for i in range(1, delay):
+            dl.accept_ratio(inv_d, ks_d[i - 1], phi_d, ks_d[i], phi_d, out=r_d)
+        dl.accept(inv_d, ks_d[delay - 1], phi_d)
+        dl.flush(inv_d)
+
+    ms_dlu_fused, _ = time_steps(torch, dlu_batch_fused, max(3, args.steps // 5), 1)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dlu_batch_fused()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g_dlu_f = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_dlu_f):
+        dlu_batch_fused()
+    ms_dlu_fused_graph, _ = time_steps(torch, g_dlu_f.replay, max(3, args.steps // 5), 1)
+    del dl, g_dlu, g_dlu_f
     del s32, rows_d, Dbuf, Rbuf, rows_np, inv_d, phi_d
     torch.cuda.empty_cache()
     bpu_rvgl = 64 * 4 + 4 + 20.0 / N
@@ -397,9 +416,15 @@ def main() -> int:
                                     ms_sm / (ms_dlu / delay),
                                     "ms_per_16_moves_graph": ms_dlu_graph, "ms_per_move_graph": ms_dlu_graph / delay,
                                     "speedup_per_move_vs_sherman_morrison_graph": ms_sm / (ms_dlu_graph / delay),
+                                    "ms_per_16_moves_fused": ms_dlu_fused,
+                                    "ms_per_16_moves_fused_graph": ms_dlu_fused_graph,
+                                    "ms_per_move_fused_graph": ms_dlu_fused_graph / delay,
+                                    "speedup_per_move_vs_sherman_morrison_fused_graph":
+                                        ms_sm / (ms_dlu_fused_graph / delay),
                                     "note": "each move: ratio against the pending moves + accept; one flush per "
                                             "16 moves (all included); _graph: the 16 moves and the flush replayed "
-                                            "from one HIP graph"},
+                                            "from one HIP graph; _fused: each accept in the same launch as the "
+                                            "next move's ratio"},
              "f32_locality_sorted": {
                  "evals_per_s": units / (ms_sorted * 1e-3), "ms_per_step": ms_sorted, "tile": list(stile32),
                  "speedup_vs_f32": ms32 / ms_sorted, "bitwise_equal_to_f32": same32,

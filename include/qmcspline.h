@@ -266,6 +266,13 @@ int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const in
  *     and border S^-1 (the Schur complement is the ratio); k = -1 marks a
  *     rejected move, and a slot whose walker is out of range is skipped.  At most `delay` accept calls between flushes
  *     (SPL_EINVAL otherwise); a walker may appear once per call.
+ *   spline_dlu_accept_ratio: one call for the accept of the previous move
+ *     (k_acc[s], V_acc[s], as spline_dlu_accept) followed by the ratio of the
+ *     next proposal (k[s], V/G/L[s], as spline_dlu_ratio) in slot s, for a
+ *     step loop that evaluates the next proposal's orbitals before the
+ *     previous move's accept; results equal the two calls bit for bit, in
+ *     one launch (two when S^-1 does not fit in LDS).  k_acc[s] < 0: nothing
+ *     to accept; k[s] must not be pending after the accept.
  *   spline_dlu_flush: A^-1 -= (A^-1 Phi - Q) S^-1 R for every walker (R: rows
  *     k_l of A^-1, Q: columns e_{k_l}), then no move is pending.  ainv must
  *     hold the inverses of all `walkers` walkers of the workspace.
@@ -280,6 +287,10 @@ int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv_dev, int64_t walke
                      void* stream);
 int spline_dlu_accept(spline_dlu_t* h, const float* ainv_dev, int64_t walker_stride, const int32_t* walkers_dev,
                       const int32_t* k_dev, const float* V, int64_t count, void* stream);
+int spline_dlu_accept_ratio(spline_dlu_t* h, const float* ainv_dev, int64_t walker_stride,
+                            const int32_t* walkers_dev, const int32_t* k_acc_dev, const float* V_acc,
+                            const int32_t* k_dev, const float* V, const float* G, const float* L, int64_t count,
+                            float* out, void* stream);
 int spline_dlu_flush(spline_dlu_t* h, float* ainv_dev, int64_t walker_stride, void* stream);
 
 /* General (triclinic) cells.

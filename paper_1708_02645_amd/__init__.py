@@ -86,6 +86,7 @@ def lib():
             "spline_dlu_destroy": ([p], ctypes.c_int),
             "spline_dlu_ratio": ([p, p, i64, p, p, p, p, p, i64, p, p], ctypes.c_int),
             "spline_dlu_accept": ([p, p, i64, p, p, p, i64, p], ctypes.c_int),
+            "spline_dlu_accept_ratio": ([p, p, i64, p, p, p, p, p, p, p, i64, p, p], ctypes.c_int),
             "spline_dlu_flush": ([p, p, i64, p], ctypes.c_int),
             "spline_set_lattice": ([p, p], ctypes.c_int),
             "spline_get_lattice": ([p, p], ctypes.c_int),
@@ -1066,6 +1067,27 @@ class DelayedUpdate:
             sp, _ = _stream_ptr(t, self.device, stream)
             check(lib().spline_dlu_accept(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers), self._p(k),
                                           self._p(V), count, sp))
+
+    def accept_ratio(self, ainv, k_acc, V_acc, k, V, G=None, L=None, walkers=None, out=None, stream=None):
+        """accept(ainv, k_acc, V_acc) then ratio(ainv, k, V, G, L) in one launch
+        (bit-identical to the two calls)."""
+        t = self._torch
+        count = self._slots(k, V, walkers)
+        if self._slots(k_acc, V_acc, walkers) != count:
+            raise ValueError("accepted and proposed slots differ in count")
+        if (G is None) != (L is None):
+            raise ValueError("give both G and L, or neither")
+        if G is not None and (tuple(G.shape) != (count, 3, self.n) or tuple(L.shape) != (count, self.n)
+                              or not G.is_contiguous() or not L.is_contiguous()):
+            raise ValueError("G [count, 3, n] and L [count, n] must be contiguous")
+        shape = (count, 5) if G is not None else (count,)
+        out = out if out is not None else t.empty(shape, dtype=t.float32, device=self.device)
+        with t.cuda.device(self.device):
+            sp, _ = _stream_ptr(t, self.device, stream)
+            check(lib().spline_dlu_accept_ratio(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers),
+                                                self._p(k_acc), self._p(V_acc), self._p(k), self._p(V), self._p(G),
+                                                self._p(L), count, self._p(out), sp))
+        return out
 
     def flush(self, ainv, stream=None):
         t = self._torch

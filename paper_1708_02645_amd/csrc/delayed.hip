@@ -62,6 +62,8 @@ struct DluArgs {
     float* out;
     int32_t stage_sinv;  // ratio / accept: copy S^-1 to LDS first (when it fits beside the rest)
     int64_t nwalkers;    // walkers of the workspace: a slot's walker must be in [0, nwalkers)
+    const int32_t* kacc; // accepting step: electron of the move accepted in slot s (< 0: none)
+    const float* Vacc;   //   and its orbital values [count][n]
 };
 
 __device__ inline float dwave_sum(float x)
@@ -152,134 +154,187 @@ __device__ inline void dlu_copy_rows(float* rows, const float* const (&src)[NR],
     }
 }
 
-// The staging shared by ratio and accept, in two rounds of memory traffic:
-// first the slot and the orbital quantities of the proposed position (they
-// depend on the slot alone), then, for a valid slot, the pending count, the
-// electrons K, S^-1 (whole d x d block, when staged) and row k of A0^-1.
-// Returns false for a rejected or out-of-range slot (k outside [0, n) or a
-// walker outside [0, walkers)).
-template <int NQ>
-__device__ inline bool dlu_stage(const DluArgs& a, int64_t s, float* as, float* qs, int32_t* Ks, float* Ss,
-                                 float*& st, float*& A, int& k, int& j)
+// `cnt` dot products of LDS vectors, p1[e] . p2[e], one wave each, in the
+// order of dlu_dots (lane-strided over m, then a butterfly), so a dot formed
+// here equals the same dot formed there bit for bit.
+__device__ inline void dlu_lds_dots(const float* const* p1, const float* const* p2, float* const* dst, int cnt,
+                                    int n)
 {
-    const int n = a.n, tid = threadIdx.x;
-    k = a.k[s];
-    const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
-    if constexpr (NQ == 5) {
-        const float* const src[5] = {a.V + s * n, a.G + (3 * s) * n, a.G + (3 * s + 1) * n, a.G + (3 * s + 2) * n,
-                                     a.L_ + s * n};
-        dlu_copy_rows<5>(qs, src, n);
-    } else {
-        const float* const src[1] = {a.V + s * n};
-        dlu_copy_rows<1>(qs, src, n);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = wave; e < cnt; e += kDThreads / 64) {
+        float s = 0.f;
+        for (int m = lane; m < n; m += 64) s = fmaf(p1[e][m], p2[e][m], s);
+        s = dwave_sum(s);
+        if (lane == 0) *dst[e] = s;
     }
-    if (k < 0 || k >= n || w < 0 || w >= a.nwalkers) return false;
-    st = a.ws + w * a.L.stride;
-    A = a.ainv + w * a.wstride;
-    j = reinterpret_cast<const int32_t*>(st + a.L.cnt)[0];
-    if (tid < a.d) Ks[tid] = reinterpret_cast<const int32_t*>(st + a.L.k)[tid];
-    if (a.stage_sinv)
-        for (int e = tid; e < a.d * a.d; e += kDThreads) Ss[e] = st[a.L.sinv + e];
-    const float* const row[1] = {A + (int64_t)k * n};
-    dlu_copy_rows<1>(as, row, n);
-    return true;
 }
 
-template <int NQ>
-__global__ __launch_bounds__(kDThreads) void dlu_ratio_kernel(DluArgs a)
+// One step of the delayed update for slot s, in one workgroup: optionally
+// accept the move kacc[s] (append phi = Vacc[s], border S^-1 with the Schur
+// complement, which is that move's ratio), then optionally form the ratio
+// (and derivative sums) of the proposal k[s] with quantities V/G/L[s]
+// against the pending moves, the one just accepted included.  Memory is
+// read in two rounds: the slot and the orbital rows first (they depend on
+// the slot alone), then the pending count, electrons, S^-1 and the rows k of
+// A0^-1.  The move accepted here enters the ratio from LDS (its phi and its
+// row of A0^-1), in the order of the dot products of a separate ratio call,
+// so a fused step equals an accept followed by a ratio bit for bit.
+// ACCEPT alone is spline_dlu_accept, RATIO alone spline_dlu_ratio.  A fused
+// step needs S^-1 staged in LDS (the host checks).
+template <int NQ, bool ACCEPT, bool RATIO>
+__global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
 {
     extern __shared__ float lds[];
     const int n = a.n, tid = threadIdx.x, d = a.d;
     const int64_t s = blockIdx.x;
-    float* as = lds;                                   // a_k [n]
-    float* qs = as + n;                                // q [NQ][n]
-    float* x = qs + NQ * n;                            // [NQ]
-    float* t = x + NQ;                                 // [d]
-    float* y = t + d;                                  // [d][NQ]
-    float* u = y + d * NQ;                             // [d]
-    int32_t* Ks = reinterpret_cast<int32_t*>(u + d);   // [d]
-    float* Ss = reinterpret_cast<float*>(Ks + d);      // S^-1 [d][d] when staged
-    float *st, *A;
-    int k, j;
-    if (!dlu_stage<NQ>(a, s, as, qs, Ks, Ss, st, A, k, j)) {
-        if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
-        return;
-    }
-    const float* Sr = a.stage_sinv ? Ss : st + a.L.sinv;  // row stride d either way
-    __syncthreads();
-    dlu_dots<NQ>(a, A, st, j, Ks, as, qs, x, t, y);
-    __syncthreads();
-    if (tid < j) {  // u = t^T S^-1
-        float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * d + tid], v);
-        u[tid] = v;
-    }
-    __syncthreads();
-    if (tid < NQ) {
-        float r = x[tid];
-        for (int l = 0; l < j; ++l) r = fmaf(-u[l], y[l * NQ + tid], r);
-        a.out[s * NQ + tid] = r;
-    }
-}
-
-__global__ __launch_bounds__(kDThreads) void dlu_accept_kernel(DluArgs a)
-{
-    extern __shared__ float lds[];
-    const int n = a.n, tid = threadIdx.x, d = a.d;
-    const int64_t s = blockIdx.x;
-    float* as = lds;
-    float* qs = as + n;                                // v [n]
-    float* x = qs + n;                                 // [1]
-    float* t = x + 1;                                  // [d]
-    float* y = t + d;                                  // [d]
-    float* u = y + d;                                  // [d]  t^T S^-1
-    float* w = u + d;                                  // [d]  S^-1 y
-    float* rho = w + d;                                // [1]
+    float* qa = lds;                                   // accepted phi [n]
+    float* aa = qa + (ACCEPT ? n : 0);                 // row kacc of A0^-1 [n]
+    float* ar = aa + (ACCEPT ? n : 0);                 // row k of A0^-1 [n]
+    float* qs = ar + (RATIO ? n : 0);                  // q [NQ][n]
+    float* sc = qs + (RATIO ? NQ * n : 0);             // scalars:
+    float* x = sc;                                     //   ratio: x [NQ]
+    float* t = x + NQ;                                 //   t [d + 1]
+    float* y = t + d + 1;                              //   y [d + 1][NQ]
+    float* u = y + (d + 1) * NQ;                       //   u [d + 1]
+    float* xa = u + d + 1;                             //   accept: x [1], t [d], y [d], u [d], w [d], rho [1]
+    float* ta = xa + 1;
+    float* ya = ta + d;
+    float* ua = ya + d;
+    float* wa = ua + d;
+    float* rho = wa + d;
     int32_t* Ks = reinterpret_cast<int32_t*>(rho + 1);  // [d]
     float* Ss = reinterpret_cast<float*>(Ks + d);      // S^-1 [d][d] when staged
-    float *st, *A;
-    int k, j;
-    if (!dlu_stage<1>(a, s, as, qs, Ks, Ss, st, A, k, j)) return;
-    if (j >= d) return;  // the host keeps accepts between flushes <= d
+
+    // round 1: the slot and the orbital rows
+    const int k_a = ACCEPT ? a.kacc[s] : -1;
+    const int k_r = RATIO ? a.k[s] : -1;
+    const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
+    if constexpr (RATIO) {
+        if constexpr (NQ == 5) {
+            const float* const src[5] = {a.V + s * n, a.G + (3 * s) * n, a.G + (3 * s + 1) * n,
+                                         a.G + (3 * s + 2) * n, a.L_ + s * n};
+            dlu_copy_rows<5>(qs, src, n);
+        } else {
+            const float* const src[1] = {a.V + s * n};
+            dlu_copy_rows<1>(qs, src, n);
+        }
+    }
+    if constexpr (ACCEPT) {
+        const float* const src[1] = {a.Vacc + s * n};
+        dlu_copy_rows<1>(qa, src, n);
+    }
+    const bool wok = w >= 0 && w < a.nwalkers;
+    const bool acc_ok = ACCEPT && wok && k_a >= 0 && k_a < n;
+    const bool rat_ok = RATIO && wok && k_r >= 0 && k_r < n;
+    if (!acc_ok && !rat_ok) {
+        if (RATIO && tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
+        return;
+    }
+    // round 2: the pending state and the rows of A0^-1
+    float* st = a.ws + w * a.L.stride;
+    const float* A = a.ainv + w * a.wstride;
+    int32_t* cnt = reinterpret_cast<int32_t*>(st + a.L.cnt);
     float* Sinv = st + a.L.sinv;
+    const int j = cnt[0];
+    if (tid < d) Ks[tid] = reinterpret_cast<const int32_t*>(st + a.L.k)[tid];
+    if (a.stage_sinv)
+        for (int e = tid; e < d * d; e += kDThreads) Ss[e] = Sinv[e];
+    if (acc_ok) {
+        const float* const row[1] = {A + (int64_t)k_a * n};
+        dlu_copy_rows<1>(aa, row, n);
+    }
+    if (rat_ok) {
+        const float* const row[1] = {A + (int64_t)k_r * n};
+        dlu_copy_rows<1>(ar, row, n);
+    }
     const float* Sr = a.stage_sinv ? Ss : Sinv;  // row stride d either way
     __syncthreads();
-    dlu_dots<1>(a, A, st, j, Ks, as, qs, x, t, y);
-    __syncthreads();
-    if (tid < j) {
-        float v = 0.f;
-        for (int i = 0; i < j; ++i) v = fmaf(t[i], Sr[i * d + tid], v);
-        u[tid] = v;
-    } else if (tid >= 64 && tid < 64 + j) {
-        const int i = tid - 64;
-        float v = 0.f;
-        for (int l = 0; l < j; ++l) v = fmaf(Sr[i * d + l], y[l], v);
-        w[i] = v;
+
+    int jr = j;  // pending moves the ratio sees
+    if (acc_ok && j < d) {  // the host keeps accepts between flushes <= d
+        dlu_dots<1>(a, A, st, j, Ks, aa, qa, xa, ta, ya);
+        __syncthreads();
+        if (tid < j) {
+            float v = 0.f;
+            for (int i = 0; i < j; ++i) v = fmaf(ta[i], Sr[i * d + tid], v);
+            ua[tid] = v;
+        } else if (tid >= 64 && tid < 64 + j) {
+            const int i = tid - 64;
+            float v = 0.f;
+            for (int l = 0; l < j; ++l) v = fmaf(Sr[i * d + l], ya[l], v);
+            wa[i] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {  // the Schur complement: the same value as the ratio of this move
+            float r = xa[0];
+            for (int l = 0; l < j; ++l) r = fmaf(-ua[l], ya[l], r);
+            rho[0] = r;
+        }
+        __syncthreads();
+        const float ir = 1.f / rho[0];
+        const int j1 = j + 1;
+        for (int e = tid; e < j1 * j1; e += kDThreads) {
+            const int i = e / j1, l = e - i * j1;
+            float v;
+            if (i < j && l < j) v = fmaf(wa[i] * ua[l], ir, Sr[i * d + l]);
+            else if (i < j) v = -wa[i] * ir;
+            else if (l < j) v = -ua[l] * ir;
+            else v = ir;
+            Sinv[i * d + l] = v;
+            if (RATIO) Ss[i * d + l] = v;  // the ratio below reads the bordered S^-1 from LDS
+        }
+        float* Phi = st + a.L.phi + (int64_t)j * n;
+        for (int m = tid; m < n; m += kDThreads) Phi[m] = qa[m];
+        if (tid == 0) {
+            reinterpret_cast<int32_t*>(st + a.L.k)[j] = k_a;
+            Ks[j] = k_a;
+            cnt[0] = j + 1;
+        }
+        jr = j + 1;
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) {  // the Schur complement: the same value as the ratio kernel's
-        float r = x[0];
-        for (int l = 0; l < j; ++l) r = fmaf(-u[l], y[l], r);
-        rho[0] = r;
+    if constexpr (RATIO) {
+        if (!rat_ok) {
+            if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
+            return;
+        }
+        dlu_dots<NQ>(a, A, st, j, Ks, ar, qs, x, t, y);  // x, and the moves pending before this step
+        if (jr > j) {  // the move accepted above, from LDS: t_j = a_k . phi_j, y_j = a_{k_j} . q
+            const float* p1[NQ + 1];
+            const float* p2[NQ + 1];
+            float* dst[NQ + 1];
+            p1[0] = ar;
+            p2[0] = qa;
+            dst[0] = t + j;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                p1[q + 1] = aa;
+                p2[q + 1] = qs + q * n;
+                dst[q + 1] = y + j * NQ + q;
+            }
+            dlu_lds_dots(p1, p2, dst, NQ + 1, n);
+        }
+        __syncthreads();
+        if (tid < jr) {  // u = t^T S^-1
+            float v = 0.f;
+            for (int i = 0; i < jr; ++i) v = fmaf(t[i], Sr[i * d + tid], v);
+            u[tid] = v;
+        }
+        __syncthreads();
+        if (tid < NQ) {
+            float r = x[tid];
+            for (int l = 0; l < jr; ++l) r = fmaf(-u[l], y[l * NQ + tid], r);
+            a.out[s * NQ + tid] = r;
+        }
     }
-    __syncthreads();
-    const float ir = 1.f / rho[0];
-    const int j1 = j + 1;
-    for (int e = tid; e < j1 * j1; e += kDThreads) {
-        const int i = e / j1, l = e - i * j1;
-        float* p = Sinv + i * d + l;
-        if (i < j && l < j) *p = fmaf(w[i] * u[l], ir, Sr[i * d + l]);
-        else if (i < j) *p = -w[i] * ir;
-        else if (l < j) *p = -u[l] * ir;
-        else *p = ir;
-    }
-    float* Phi = st + a.L.phi + (int64_t)j * n;
-    for (int m = tid; m < n; m += kDThreads) Phi[m] = qs[m];
-    __syncthreads();
-    if (tid == 0) {
-        reinterpret_cast<int32_t*>(st + a.L.k)[j] = k;
-        reinterpret_cast<int32_t*>(st + a.L.cnt)[0] = j + 1;
-    }
+}
+
+// LDS bytes of a step kernel (without S^-1)
+static size_t dlu_step_lds(int n, int d, int nq, bool acc, bool rat)
+{
+    const size_t rows = (acc ? 2 : 0) + (rat ? 1 + nq : 0);
+    const size_t scal = nq + (size_t)(d + 1) * (nq + 2) + 1 + 4 * (size_t)d + 1;
+    return sizeof(float) * (rows * n + scal) + sizeof(int32_t) * d;
 }
 
 // Flush, step 1: M = S^-1 R (R = rows K_i of A0^-1, read before any row
@@ -812,11 +867,11 @@ int spline_dlu_ratio(const spline_dlu_t* h, const float* ainv, int64_t walker_st
     DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
     a.nwalkers = h->walkers;
     void* params[] = {&a};
-    const int nq = vgl ? 5 : 1;
-    size_t lds = sizeof(float) * ((size_t)(1 + nq) * h->n + nq + (size_t)h->d * (nq + 3));
+    size_t lds = dlu_step_lds(h->n, h->d, vgl ? 5 : 1, false, true);
     a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
     if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
-    QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_ratio_kernel<5> : (const void*)&dlu_ratio_kernel<1>,
+    QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_step_kernel<5, false, true>
+                               : (const void*)&dlu_step_kernel<1, false, true>,
                            dim3((unsigned)count), dim3(kDThreads), params, lds, static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
     return SPL_OK;
@@ -832,15 +887,51 @@ int spline_dlu_accept(spline_dlu_t* h, const float* ainv, int64_t walker_stride,
     if (!k || !V) return fail(SPL_EINVAL, "NULL electron or value pointer");
     if (h->accepts >= h->d) return fail(SPL_EINVAL, "delay reached: flush before accepting more moves");
     if (!walkers && count > h->walkers) return fail(SPL_EINVAL, "count exceeds the workspace's walkers");
-    DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, nullptr, nullptr,
-              count, nullptr};
+    DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, nullptr, nullptr, nullptr,
+              nullptr, count, nullptr};
     a.nwalkers = h->walkers;
+    a.kacc = k;
+    a.Vacc = V;
     void* params[] = {&a};
-    size_t lds = sizeof(float) * (2 * (size_t)h->n + 2 + 5 * (size_t)h->d);
+    size_t lds = dlu_step_lds(h->n, h->d, 1, true, false);
     a.stage_sinv = lds + sizeof(float) * h->d * h->d <= kDMaxLds;
     if (a.stage_sinv) lds += sizeof(float) * h->d * h->d;
-    QS_HIP(hipLaunchKernel((const void*)&dlu_accept_kernel, dim3((unsigned)count), dim3(kDThreads), params, lds,
-                           static_cast<hipStream_t>(stream)));
+    QS_HIP(hipLaunchKernel((const void*)&dlu_step_kernel<1, true, false>, dim3((unsigned)count), dim3(kDThreads),
+                           params, lds, static_cast<hipStream_t>(stream)));
+    QS_HIP(hipGetLastError());
+    ++h->accepts;
+    return SPL_OK;
+}
+
+int spline_dlu_accept_ratio(spline_dlu_t* h, const float* ainv, int64_t walker_stride, const int32_t* walkers,
+                            const int32_t* k_acc, const float* V_acc, const int32_t* k, const float* V,
+                            const float* G, const float* L, int64_t count, float* out, void* stream)
+{
+    int rc = dlu_check(h, ainv, walker_stride);
+    if (rc) return rc;
+    if (count < 0 || count > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "bad count");
+    if (count == 0) return SPL_OK;
+    if (!k_acc || !V_acc || !k || !V || !out) return fail(SPL_EINVAL, "NULL electron, value or output pointer");
+    if ((G == nullptr) != (L == nullptr)) return fail(SPL_EINVAL, "give both G and L, or neither");
+    if (h->accepts >= h->d) return fail(SPL_EINVAL, "delay reached: flush before accepting more moves");
+    if (!walkers && count > h->walkers) return fail(SPL_EINVAL, "count exceeds the workspace's walkers");
+    const bool vgl = G != nullptr;
+    const int nq = vgl ? 5 : 1;
+    const size_t lds = dlu_step_lds(h->n, h->d, nq, true, true) + sizeof(float) * h->d * h->d;
+    if (lds > kDMaxLds) {  // S^-1 would not fit in LDS beside the rest: the same step as two launches
+        rc = spline_dlu_accept(h, ainv, walker_stride, walkers, k_acc, V_acc, count, stream);
+        if (rc) return rc;
+        return spline_dlu_ratio(h, ainv, walker_stride, walkers, k, V, G, L, count, out, stream);
+    }
+    DluArgs a{h->ws, h->L, h->n, h->d, const_cast<float*>(ainv), walker_stride, walkers, k, V, G, L, count, out};
+    a.nwalkers = h->walkers;
+    a.kacc = k_acc;
+    a.Vacc = V_acc;
+    a.stage_sinv = 1;
+    void* params[] = {&a};
+    QS_HIP(hipLaunchKernel(vgl ? (const void*)&dlu_step_kernel<5, true, true>
+                               : (const void*)&dlu_step_kernel<1, true, true>,
+                           dim3((unsigned)count), dim3(kDThreads), params, lds, static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
     ++h->accepts;
     return SPL_OK;

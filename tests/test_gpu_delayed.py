@@ -212,3 +212,44 @@ def test_argument_errors(torch, q):
     rc = L.spline_dlu_accept(dl._h, ctypes.c_void_p(a.data_ptr()), 64, None, ctypes.c_void_p(k3.data_ptr()),
                              ctypes.c_void_p(V3.data_ptr()), 3, None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("n,delay,walkers,vgl", [(384, 16, 64, True), (129, 8, 9, False), (2048, 64, 2, True)])
+def test_fused_accept_ratio_equals_separate_calls(torch, q, n, delay, walkers, vgl):
+    """A step loop that accepts the previous move and forms the next ratio in
+    one call equals the same loop with separate accept and ratio calls, bit
+    for bit (ratios, derivative sums and the flushed inverses); 2048 / 64
+    with derivatives does not fit S^-1 in LDS and runs as two launches."""
+    rng = np.random.default_rng(n + delay)
+    A = np.eye(n) + rng.normal(size=(walkers, n, n)) * (0.3 / np.sqrt(n))
+    inv0 = np.linalg.inv(A).astype(np.float32)
+    ks = np.stack([rng.permutation(n)[:delay] for _ in range(walkers)]).astype(np.int32)
+    acc = rng.random((delay, walkers)) < 0.7
+    dev = torch.device("cuda")
+    V = [torch.from_numpy((rng.normal(size=(walkers, n)) / np.sqrt(n)).astype(np.float32)).to(dev)
+         for _ in range(delay)]
+    G = [torch.from_numpy(rng.normal(size=(walkers, 3, n)).astype(np.float32)).to(dev) if vgl else None
+         for _ in range(delay)]
+    Lp = [torch.from_numpy(rng.normal(size=(walkers, n)).astype(np.float32)).to(dev) if vgl else None
+          for _ in range(delay)]
+    kk = [torch.from_numpy(np.ascontiguousarray(ks[:, i])).to(dev) for i in range(delay)]
+    ka = [torch.from_numpy(np.where(acc[i], ks[:, i], -1).astype(np.int32)).to(dev) for i in range(delay)]
+    a1 = torch.from_numpy(inv0.copy()).to(dev)
+    a2 = torch.from_numpy(inv0.copy()).to(dev)
+    d1 = q.DelayedUpdate(n, delay, walkers)
+    d2 = q.DelayedUpdate(n, delay, walkers)
+    sep, fused = [], []
+    for i in range(delay):
+        sep.append(d1.ratio(a1, kk[i], V[i], G[i], Lp[i]).cpu().numpy())
+        d1.accept(a1, ka[i], V[i])
+    _say("case fused step", n, delay, walkers, vgl)
+    fused.append(d2.ratio(a2, kk[0], V[0], G[0], Lp[0]).cpu().numpy())
+    for i in range(1, delay):
+        fused.append(d2.accept_ratio(a2, ka[i - 1], V[i - 1], kk[i], V[i], G[i], Lp[i]).cpu().numpy())
+    d2.accept(a2, ka[delay - 1], V[delay - 1])
+    for i, (x, y) in enumerate(zip(sep, fused)):
+        np.testing.assert_array_equal(x, y, err_msg="step %d" % i)
+        assert np.isfinite(x).all()
+    d1.flush(a1)
+    d2.flush(a2)
+    np.testing.assert_array_equal(a1.cpu().numpy(), a2.cpu().numpy())
