@@ -87,6 +87,12 @@ def test_edges(torch, q):
             pos[5] = np.nan
             pos[6, 1] = np.inf
         _check_equal(torch, s, pos)
+    # degenerate grids: one point (every position in cell 0), a flat grid
+    for g_small, cell in (((1, 1, 1), (1.0, 1.0, 1.0)), ((2, 3, 1), (0.5, 1.0, 2.0))):
+        s1 = q.Spline(g_small, rng.uniform(-1, 1, g_small + (24,)), "f32", cell=cell)
+        _say("case sorted grid", g_small)
+        _check_equal(torch, s1, rng.uniform(-3, 3, (257, 3)))
+        s1.close()
     # B == 0 is a no-op; a short workspace and a general cell are refused
     e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
     s.eval_vgl_sorted(e)
@@ -104,7 +110,7 @@ def test_edges(torch, q):
         s.eval_ratio_vgl_sorted(pos, torch.zeros((64, 40), dtype=torch.float32, device="cuda"))
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_vgh_and_general_cells_equal(torch, q, oracle, dtype):
     """VGH (orthorhombic and a triclinic cell) and the general-cell VGL in
     locality order equal the plain entry points bit for bit; the triclinic
