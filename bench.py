@@ -534,6 +534,10 @@ def main() -> int:
         "ms_per_step": ms_c2, "evals_per_s": u2 / (ms_c2 * 1e-3), "tile": list(s2.get_tile()),
         "algorithmic_GBs": u2 * BYTES_PER_UNIT["f32"] / (ms_c2 * 1e-3) / 1e9, "mall_resident_read_GBs": mall_read,
         "frac_of_mall_read": u2 * BYTES_PER_UNIT["f32"] / (ms_c2 * 1e-3) / 1e9 / mall_read}
+    st2 = s2.autotune_sorted(p2, reps=3, out=o2, cache_path=TUNE_CACHE if args.use_tune_cache else None)
+    ms_c2s, _ = time_steps(torch, lambda: s2.eval_vgl_sorted(p2, out=o2), args.steps, args.warmup)
+    forms["c2_f32_locality_sorted"] = {"ms_per_step": ms_c2s, "evals_per_s": u2 / (ms_c2s * 1e-3), "tile": list(st2),
+                                       "speedup_vs_c2_f32": ms_c2 / ms_c2s}
     del s2, o2, p2, c2coef
     s48 = q.Spline(grid, np.ascontiguousarray(coefs[..., :48]), "f32", device=dev)
     o48 = s48.alloc_outputs(B)
