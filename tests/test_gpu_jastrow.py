@@ -219,3 +219,18 @@ def test_edges(torch, q):
     assert not np.array_equal(after[1], before[1].cpu().numpy())
     with pytest.raises(q.SplineError):
         q.Jastrow((1.0, 1.0, 1.0), d["ions"], d["species"], [(d["f1"][0][0], 0.7)] * 2, d["uu"], d["ud"], 16, 8)
+
+
+def test_move_same_for_any_batch_size(torch, q):
+    """A move's result does not depend on the batch it is in (one wave per
+    move, whatever the batch size)."""
+    J, S, d = _make(q, n_elec=384, n_up=192)
+    rng = np.random.default_rng(5)
+    Wn = 1100
+    R = W.make_electrons(Wn, 384)
+    Rd = J.positions(R)
+    kk = torch.from_numpy(rng.integers(0, 384, Wn).astype(np.int32)).cuda()
+    rn = torch.from_numpy(rng.random((Wn, 3))).cuda()
+    big = J.move(Rd, kk, rn).cpu().numpy()
+    small = J.move(Rd[:64].contiguous(), kk[:64].contiguous(), rn[:64].contiguous()).cpu().numpy()
+    np.testing.assert_array_equal(big[:64], small)
