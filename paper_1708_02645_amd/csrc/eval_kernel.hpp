@@ -299,15 +299,26 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
 
         // Tiles divide the row exactly (checked on the host), so every chunk
         // is inside the table.
+        // LPP = 64: the row address is wave-uniform (scalar registers) and each
+        // lane adds its 32-bit offset.  Otherwise each lane keeps one 64-bit
+        // address for its item and adds the wave-uniform row offset: one
+        // vector add per row.
         const unsigned char* base = a.table + off;
+        const unsigned char* lbase = base + loff;
         auto issue = [&](int xy, Chunk<CW> (&buf)[4][NCH]) {
             const int k0 = xy >> 2, k1 = xy & 3;
-            const unsigned char* pr = base + k0 * a.xstride + k1 * a.ystride;
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
-                const unsigned char* row = pr + k2 * a.row_bytes;
+                const int64_t ro = k0 * a.xstride + k1 * a.ystride + k2 * a.row_bytes;
+                if constexpr (LPP == 64) {
+                    const unsigned char* row = base + ro;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + (loff + (uint32_t)(c * GCB)));
+                    for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + (loff + (uint32_t)(c * GCB)));
+                } else {
+                    const unsigned char* row = lbase + ro;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + c * GCB);
+                }
             }
         };
 
@@ -328,6 +339,17 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
         }
         // z weights of the anchored value: s0 = c1 + wa0 d0 + wa1 d1 + wa2 d2.
         const TA wa0 = -wz[0], wa1 = wz[2] + wz[3], wa2 = wz[3];
+        // Tail sums of the cubic weights, c_k = b_k + ... + b_3 (c_0 = 1): a
+        // smoothed value sum_k b_k f_k equals f_0 + sum_{k>=1} c_k (f_k - f_{k-1}),
+        // so the y and x levels smooth values from the same first differences
+        // their derivative sums use.
+        const TA cy3 = wy[3], cy2 = wy[2] + cy3, cy1 = wy[1] + cy2;
+        const TA cy[4] = {TA(1), cy1, cy2, cy3};
+        TA cx[4];
+        cx[3] = (LPP == 64) ? uniform<TA>(w.w[0][3]) : w.w[0][3];
+#pragma unroll
+        for (int k = 2; k >= 1; --k) cx[k] = ((LPP == 64) ? uniform<TA>(w.w[0][k]) : w.w[0][k]) + cx[k + 1];
+        cx[0] = TA(1);
 
         // Software pipeline over the 16 pairs (x-major), fully unrolled so that
         // every weight index is static: the loads of pair xy+1 are issued, then
@@ -356,20 +378,25 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
                     TA lz = wa0 * d0;       // z-smoothed value = hz + lz
                     lz = fma(wa1, d1, lz);
                     lz = fma(wa2, d2, lz);
+                    TA s1 = TA(0), s2 = TA(0);
                     if constexpr (VGL) {
-                        TA s1 = wz[4] * d0;
+                        s1 = wz[4] * d0;
                         s1 = fma(wz[5], d1, s1);
                         s1 = fma(wz[6], d2, s1);
-                        TA s2 = wz[7] * (d1 - d0);
+                        s2 = wz[7] * (d1 - d0);
                         s2 = fma(wz[8], d2 - d1, s2);
-                        if (y == 0) {
-                            h0[v] = hz;
-                            ul[v] = wy[0] * lz;
+                    }
+                    if (y == 0) {
+                        h0[v] = hz;
+                        ul[v] = lz;  // s0[0] = h0 + ul
+                        if constexpr (VGL) {
                             t1[v] = wy[0] * s1;
                             t2[v] = wy[0] * s2;
-                        } else {
-                            const TA e = (hz - hp[v]) + (lz - lp[v]);  // s0[y] - s0[y-1]
-                            ul[v] = fma(wy[y], (hz - h0[v]) + lz, ul[v]);
+                        }
+                    } else {
+                        const TA e = (hz - hp[v]) + (lz - lp[v]);  // s0[y] - s0[y-1]
+                        ul[v] = fma(cy[y], e, ul[v]);
+                        if constexpr (VGL) {
                             t1[v] = fma(wy[y], s1, t1[v]);
                             t2[v] = fma(wy[y], s2, t2[v]);
                             if (y == 1) {
@@ -382,40 +409,38 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
                             ep[v] = e;
                             pin(uy[v]);
                             pin(ep[v]);
+                            pin(t1[v]);
+                            pin(t2[v]);
                         }
-                        hp[v] = hz;
-                        lp[v] = lz;
-                        pin(ul[v]);
-                        pin(t1[v]);
-                        pin(t2[v]);
-                        pin(hp[v]);
-                        pin(lp[v]);
-                    } else {
-                        if (y == 0) {
-                            h0[v] = hz;
-                            ul[v] = wy[0] * lz;
-                        } else {
-                            ul[v] = fma(wy[y], (hz - h0[v]) + lz, ul[v]);
-                        }
-                        pin(ul[v]);
                     }
+                    hp[v] = hz;
+                    lp[v] = lz;
+                    pin(ul[v]);
+                    pin(hp[v]);
+                    pin(lp[v]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
 
             // Fold this x into the running sums.  u = h0 + ul is the
-            // y,z-smoothed value at this x.
-            const TA bx = (LPP == 64) ? uniform<TA>(w.w[0][x]) : w.w[0][x];
+            // y,z-smoothed value at this x; the value is u[0] plus the tail
+            // weights times the differences u[x] - u[x-1].
+            [[maybe_unused]] const TA bx = (LPP == 64) ? uniform<TA>(w.w[0][x]) : w.w[0][x];
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-                vx[v] = fma(bx, h0[v] + ul[v], vx[v]);
+                TA d = TA(0);
+                if (x == 0) {
+                    vx[v] = h0[v] + ul[v];
+                } else {
+                    d = (h0[v] - hxp[v]) + (ul[v] - uxp[v]);  // u[x] - u[x-1]
+                    vx[v] = fma(cx[x], d, vx[v]);
+                }
                 if constexpr (VGL) {
                     gya[v] = fma(bx, uy[v], gya[v]);
                     gza[v] = fma(bx, t1[v], gza[v]);
                     lyz[v] = fma(bx, uyy[v] + t2[v], lyz[v]);
                     if (x >= 1) {
                         const TA qx = (LPP == 64) ? uniform<TA>(w.w[0][4 + x - 1]) : w.w[0][4 + x - 1];
-                        const TA d = (h0[v] - hxp[v]) + (ul[v] - uxp[v]);  // u[x] - u[x-1]
                         gxa[v] = fma(qx, d, gxa[v]);
                         if (x >= 2) {
                             const TA lx = (LPP == 64) ? uniform<TA>(w.w[0][7 + x - 2]) : w.w[0][7 + x - 2];
@@ -423,9 +448,9 @@ __device__ inline void eval_block(const EvalArgs& a, int64_t b0, int np, PosW<ty
                         }
                         dxp[v] = d;
                     }
-                    hxp[v] = h0[v];
-                    uxp[v] = ul[v];
                 }
+                hxp[v] = h0[v];
+                uxp[v] = ul[v];
             }
         }
         TA acc[5][VPL];

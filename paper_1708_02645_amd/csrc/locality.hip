@@ -366,6 +366,11 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
     if (rc) return rc;
     std::vector<spline_tile> cands(n);
     spline_tile_candidates(s, cands.data(), n, &n);
+    // Shorter chunks too: fewer positions in flight per XCD keep more of
+    // their shared rows in its L2.
+    for (int32_t i = 0; i < n; ++i)
+        if (cands[i].pb == 16) cands.push_back(spline_tile{cands[i].cw, cands[i].nch, cands[i].lpp, 8});
+    n = (int32_t)cands.size();
     if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
     const int64_t Bc = std::min<int64_t>(B, 512);
     const size_t nv = (size_t)Bc * s->norb * (s->store == SPL_F64 ? 8 : 4);
