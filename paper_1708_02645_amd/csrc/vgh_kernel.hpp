@@ -78,15 +78,24 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
             wy[k] = (LPP == 64) ? uniform<TA>(w.w[1][k]) : w.w[1][k];
             wz[k] = (LPP == 64) ? uniform<TA>(w.w[2][k]) : w.w[2][k];
         }
+        // Row addresses as in eval_block: wave-uniform for LPP = 64, else one
+        // 64-bit address per lane plus the wave-uniform row offset.
         const unsigned char* base = a.table + off;
+        const unsigned char* lbase = base + loff;
         auto issue = [&](int xy, Chunk<CW> (&buf)[4][NCH]) {
             const int k0 = xy >> 2, k1 = xy & 3;
-            const unsigned char* pr = base + k0 * a.xstride + k1 * a.ystride;
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
-                const unsigned char* row = pr + k2 * a.row_bytes;
+                const int64_t ro = k0 * a.xstride + k1 * a.ystride + k2 * a.row_bytes;
+                if constexpr (LPP == 64) {
+                    const unsigned char* row = base + ro;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + (loff + (uint32_t)(c * GCB)));
+                    for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + (loff + (uint32_t)(c * GCB)));
+                } else {
+                    const unsigned char* row = lbase + ro;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) buf[k2][c] = load_chunk<CW>(row + c * GCB);
+                }
             }
         };
 
@@ -101,6 +110,15 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
             hxp[v] = uxp[v] = dxp[v] = uyp[v] = t1p[v] = TA(0);
         }
         const TA wa0 = -wz[0], wa1 = wz[2] + wz[3], wa2 = wz[3];
+        // Tail sums of the cubic weights (c_0 = 1): the y and x levels smooth
+        // values as f_0 + sum_{k>=1} c_k (f_k - f_{k-1}).
+        const TA cy3 = wy[3], cy2 = wy[2] + cy3, cy1 = wy[1] + cy2;
+        const TA cy[4] = {TA(1), cy1, cy2, cy3};
+        TA cx[4];
+        cx[3] = (LPP == 64) ? uniform<TA>(w.w[0][3]) : w.w[0][3];
+#pragma unroll
+        for (int k = 2; k >= 1; --k) cx[k] = ((LPP == 64) ? uniform<TA>(w.w[0][k]) : w.w[0][k]) + cx[k + 1];
+        cx[0] = TA(1);
 
         Chunk<CW> buf[2][4][NCH];
         issue(0, buf[0]);
@@ -132,13 +150,13 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
                     s2 = fma(wz[8], d2 - d1, s2);
                     if (y == 0) {
                         h0[v] = hz;
-                        ul[v] = wy[0] * lz;
+                        ul[v] = lz;  // s0[0] = h0 + ul
                         t1[v] = wy[0] * s1;
                         t2[v] = wy[0] * s2;
                     } else {
                         const TA e = (hz - hp[v]) + (lz - lp[v]);  // s0[y] - s0[y-1]
                         const TA f = s1 - s1p[v];                   // s1[y] - s1[y-1]
-                        ul[v] = fma(wy[y], (hz - h0[v]) + lz, ul[v]);
+                        ul[v] = fma(cy[y], e, ul[v]);
                         t1[v] = fma(wy[y], s1, t1[v]);
                         t2[v] = fma(wy[y], s2, t2[v]);
                         if (y == 1) {
@@ -171,7 +189,7 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
             const TA bx = (LPP == 64) ? uniform<TA>(w.w[0][x]) : w.w[0][x];
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-                vx[v] = fma(bx, h0[v] + ul[v], vx[v]);
+                if (x == 0) vx[v] = h0[v] + ul[v];  // u[0]; then the tail weights times u[x] - u[x-1]
                 gya[v] = fma(bx, uy[v], gya[v]);
                 gza[v] = fma(bx, t1[v], gza[v]);
                 hyy[v] = fma(bx, uyy[v], hyy[v]);
@@ -180,6 +198,7 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
                 if (x >= 1) {
                     const TA qx = (LPP == 64) ? uniform<TA>(w.w[0][4 + x - 1]) : w.w[0][4 + x - 1];
                     const TA d = (h0[v] - hxp[v]) + (ul[v] - uxp[v]);  // u[x] - u[x-1]
+                    vx[v] = fma(cx[x], d, vx[v]);
                     gxa[v] = fma(qx, d, gxa[v]);
                     hxy[v] = fma(qx, uy[v] - uyp[v], hxy[v]);
                     hxz[v] = fma(qx, t1[v] - t1p[v], hxz[v]);
