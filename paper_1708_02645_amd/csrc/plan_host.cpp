@@ -22,7 +22,10 @@ __global__ void plan_reset_kernel(unsigned int* counter)
     if (threadIdx.x < kPlanSegs && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
-constexpr int kMinPb = 16;  // smallest positions-per-task; sizes the workspace
+// Smallest positions-per-task a plan may use; it sizes the task list in the
+// workspace.  Locality-ordered plans also try 8-position tasks.
+constexpr int kMinPb = 16, kMinPbSorted = 8;
+static int min_pb(bool sorted) { return sorted ? kMinPbSorted : kMinPb; }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -37,7 +40,7 @@ static bool ws_layout(int32_t n_tabs, const int64_t* B, bool sorted, WsLayout* w
     for (int32_t t = 0; t < n_tabs; ++t) {
         if (B[t] < 0) return false;
         if (sorted && B[t] > (int64_t)std::numeric_limits<int32_t>::max()) return false;
-        nt += (B[t] + kMinPb - 1) / kMinPb;
+        nt += (B[t] + min_pb(sorted) - 1) / min_pb(sorted);
         if (nt > (int64_t)1 << 30) return false;
     }
     w->counter = 0;  // kPlanSegs counters in the first 256 bytes
@@ -66,6 +69,7 @@ struct spline_plan_s {
     spline_tile tile{};
     const qs::Variant* var = nullptr;
     int32_t ntasks = 0;
+    int64_t max_tasks = 0;            // capacity of the task list in the workspace
     int32_t nblocks = 0;
     bool sorted = false;              // positions sorted on the device before each launch
     std::vector<const int32_t*> perm; // locality-ordered plans: each table's index list
@@ -100,7 +104,9 @@ static int stage_config(spline_plan_s* p, const Variant* v, const spline_tile& t
         args[i] = make_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
         if (p->sorted) args[i].idx = p->perm[i];
     }
+    if (t.pb < min_pb(p->sorted)) return fail(SPL_EINVAL, "positions per task below the plan's minimum");
     std::vector<PlanTask> tasks = make_tasks(p, t.pb);
+    if ((int64_t)tasks.size() > p->max_tasks) return fail(SPL_EINVAL, "task list larger than its workspace region");
     QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(EvalArgs),
                           hipMemcpyHostToDevice, st));
     if (!tasks.empty())
@@ -225,6 +231,7 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     p->L.assign(L, L + n_tabs);
     p->ws = static_cast<unsigned char*>(workspace_dev);
     p->lay = lay;
+    p->max_tasks = max_tasks;
     p->device = dev;
     p->sorted = sorted;
     if (sorted)  // the index lists sit at fixed places in each table's sort workspace
@@ -242,7 +249,8 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
         bool ok = true;
         for (int32_t t = 0; t < n_tabs && ok; ++t) ok = tile_fits(tabs[t], v);
         if (!ok) continue;
-        for (int pb : {16, 32, 64}) {
+        for (int pb : {8, 16, 32, 64}) {
+            if (pb == 8 && !sorted) continue;  // short tasks pay only when neighbours share rows
             if (v.lds_per_pos * (size_t)pb > 64 * 1024) continue;
             cands.push_back({&v, spline_tile{v.cw, v.nch, v.lpp, pb}});
         }

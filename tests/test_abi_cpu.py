@@ -185,3 +185,20 @@ def test_delayed_update_sizes_without_a_gpu():
     assert L.spline_dlu_workspace_bytes(384, 0, 512) == 0
     assert L.spline_dlu_workspace_bytes(8, 9, 512) == 0
     assert L.spline_dlu_ratio(None, None, 64, None, None, None, None, None, 1, None, None) == -1
+
+
+def test_sorted_plan_workspace_holds_eight_position_tasks():
+    """A locality-ordered plan may run 8-position tasks (16-byte task
+    records), a plain plan 16-position ones; the sorted plan's workspace also
+    holds each table's sort workspace (32768 bucket counts and three int32
+    per position).  Its size must cover all of that, or the task list spills
+    into the sort workspace that follows it."""
+    L = q.lib()
+    for Bs in ((196608,), (64, 1000, 4099), (7,)):
+        arr = (ctypes.c_int64 * len(Bs))(*Bs)
+        plain = L.spline_plan_workspace_bytes(len(Bs), arr)
+        srt = L.spline_plan_workspace_bytes_sorted(len(Bs), arr)
+        tasks8 = sum((b + 7) // 8 for b in Bs) * 16
+        tasks16 = sum((b + 15) // 16 for b in Bs) * 16
+        sort_ws = sum(4 * (32768 + 3 * b) for b in Bs)
+        assert srt >= plain - tasks16 + tasks8 + sort_ws, (Bs, plain, srt)
