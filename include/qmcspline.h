@@ -12,6 +12,12 @@
  * launches are asynchronous: a fault inside a kernel surfaces at the
  * caller's next synchronisation of that stream.
  *
+ * Threads: evaluation calls only read a handle and may run concurrently on
+ * one handle from several host threads; calls that change a handle (tile
+ * setters, autotuners, spline_set_lattice, spline_destroy) must not overlap
+ * any other call on that handle.  Autotuners that share a cache file should
+ * not run at the same time (each appends one line per search).
+ *
  * The method (Mathuriya et al., "Embracing a new era of highly efficient and
  * productive quantum Monte Carlo simulations", SC'17):
  *  - Section 3: each Slater matrix row A(i,j) = phi_i(r_j) needs all N

@@ -42,17 +42,19 @@ const Variant* ratio_variants_f64(int*);
 const Variant* ratio_variants_bf16(int*);
 const Variant* ratio_variants_f16(int*);
 
+// Built once, on first use (a function-local static: thread-safe).
 const Variant* variants(int* count)
 {
-    static std::vector<Variant> all;
-    if (all.empty()) {
+    static const std::vector<Variant> all = [] {
+        std::vector<Variant> a;
         for (auto f : {variants_f64, variants_f32, variants_bf16, variants_f16, ratio_variants_f64,
                        ratio_variants_f32, ratio_variants_bf16, ratio_variants_f16}) {
             int n = 0;
             const Variant* v = f(&n);
-            all.insert(all.end(), v, v + n);
+            a.insert(a.end(), v, v + n);
         }
-    }
+        return a;
+    }();
     *count = (int)all.size();
     return all.data();
 }

@@ -17,16 +17,18 @@ const VghVariant* vgh_variants_f32(int*);
 const VghVariant* vgh_variants_bf16(int*);
 const VghVariant* vgh_variants_f16(int*);
 
+// Built once, on first use (a function-local static: thread-safe).
 static const std::vector<VghVariant>& vgh_all()
 {
-    static std::vector<VghVariant> all;
-    if (all.empty()) {
+    static const std::vector<VghVariant> all = [] {
+        std::vector<VghVariant> a;
         for (auto f : {vgh_variants_f64, vgh_variants_f32, vgh_variants_bf16, vgh_variants_f16}) {
             int n = 0;
             const VghVariant* v = f(&n);
-            all.insert(all.end(), v, v + n);
+            a.insert(a.end(), v, v + n);
         }
-    }
+        return a;
+    }();
     return all;
 }
 
