@@ -169,8 +169,11 @@ def probe_stream_read(buf, grid: int = 1024, out=None, stream=None):
     device tensor (for measuring the attainable read bandwidth)."""
     import torch
 
+    if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous GPU tensor")
     if out is None:
         out = torch.empty(grid * 256, dtype=torch.float32, device=buf.device)
+    _need(out, torch.float32, (grid * 256,), buf.device, "out")
     sp, _ = _stream_ptr(torch, buf.device, stream)
     check(lib().spline_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
                                          ctypes.c_void_p(out.data_ptr()), int(grid), sp))
@@ -213,6 +216,24 @@ def _stream_ptr(torch, device, stream):
     if stream is None:
         stream = torch.cuda.current_stream(device)
     return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+def _need(t, dtype, shape, device, what):
+    """t itself if it is a contiguous tensor of this dtype, shape and device
+    (the kernels receive its raw pointer); ValueError otherwise."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.device == device and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape)):
+        raise ValueError("%s must be a contiguous %s tensor of shape %s on %s" % (what, dtype, tuple(shape), device))
+    return t
+
+
+def _need_pos(t, device, what="pos"):
+    """Positions: a contiguous float64 [B, 3] tensor on the device."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dim() == 2):
+        raise ValueError("%s must be a float64 [B, 3] tensor" % what)
+    return _need(t, torch.float64, (t.shape[0], 3), device, what)
 
 
 class Spline:
@@ -271,14 +292,33 @@ class Spline:
         return (torch.empty((B, self.norb), **kw), torch.empty((B, 3, self.norb), **kw),
                 torch.empty((B, self.norb), **kw))
 
+    def _vgl_out(self, out, B):
+        """(V, G, L) outputs for B positions: allocated, or the caller's, checked."""
+        if out is None:
+            return self.alloc_outputs(B)
+        V, G, L = out
+        return (_need(V, self.out_dtype, (B, self.norb), self.device, "V"),
+                _need(G, self.out_dtype, (B, 3, self.norb), self.device, "G"),
+                _need(L, self.out_dtype, (B, self.norb), self.device, "L"))
+
+    def _vgh_out(self, out, B):
+        if out is None:
+            return self.alloc_vgh(B)
+        V, G, H = out
+        return (_need(V, self.out_dtype, (B, self.norb), self.device, "V"),
+                _need(G, self.out_dtype, (B, 3, self.norb), self.device, "G"),
+                _need(H, self.out_dtype, (B, 6, self.norb), self.device, "H"))
+
+    def _v_out(self, out, B):
+        if out is None:
+            return self._torch.empty((B, self.norb), dtype=self.out_dtype, device=self.device)
+        return _need(out, self.out_dtype, (B, self.norb), self.device, "V")
+
     def eval_vgl(self, pos, out=None, stream=None):
         """(V[B,N], G[B,3,N], L[B,N]) at positions pos[B,3] (float64, on device)."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, L = out if out is not None else self.alloc_outputs(B)
-        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (L, (B, self.norb))):
-            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
-                raise ValueError("output tensor has wrong shape/dtype/device")
+        V, G, L = self._vgl_out(out, B)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_vgl(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()),
@@ -289,9 +329,7 @@ class Spline:
         """V[B,N] at positions pos[B,3] (value only)."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V = out if out is not None else self._torch.empty((B, self.norb), dtype=self.out_dtype, device=self.device)
-        if tuple(V.shape) != (B, self.norb) or V.dtype != self.out_dtype or not V.is_contiguous():
-            raise ValueError("output tensor has wrong shape/dtype")
+        V = self._v_out(out, B)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_v(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()), sp))
@@ -305,9 +343,11 @@ class Spline:
                 ws = self._torch.empty(max(nb, 256), dtype=self._torch.uint8, device=self.device)
                 self._sws = ws
             workspace = ws
-        if workspace.numel() < nb or workspace.device != self.device:
-            raise ValueError("workspace too small or on another device")
-        return ctypes.c_void_p(workspace.data_ptr()), workspace.numel()
+        torch = self._torch
+        if not (isinstance(workspace, torch.Tensor) and workspace.device == self.device and workspace.is_contiguous()
+                and workspace.numel() * workspace.element_size() >= nb):
+            raise ValueError("workspace must be a contiguous tensor of >= %d bytes on %s" % (nb, self.device))
+        return ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
 
     def eval_vgl_sorted(self, pos, out=None, workspace=None, stream=None):
         """eval_vgl in locality order (same results bit for bit, faster for
@@ -315,10 +355,7 @@ class Spline:
         when not given."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, L = out if out is not None else self.alloc_outputs(B)
-        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (L, (B, self.norb))):
-            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
-                raise ValueError("output tensor has wrong shape/dtype/device")
+        V, G, L = self._vgl_out(out, B)
         wp, wn = self._sorted_ws(B, workspace)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
@@ -341,7 +378,7 @@ class Spline:
         """Tile shape of the locality-ordered VGL path (see spline_autotune_sorted)."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, L = out if out is not None else self.alloc_outputs(B)
+        V, G, L = self._vgl_out(out, B)
         wp, wn = self._sorted_ws(B, workspace)
         t = Tile()
         with self._torch.cuda.device(self.device):
@@ -357,9 +394,7 @@ class Spline:
         """eval_v in locality order (same results bit for bit)."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V = out if out is not None else self._torch.empty((B, self.norb), dtype=self.out_dtype, device=self.device)
-        if tuple(V.shape) != (B, self.norb) or V.dtype != self.out_dtype or not V.is_contiguous():
-            raise ValueError("output tensor has wrong shape/dtype")
+        V = self._v_out(out, B)
         wp, wn = self._sorted_ws(B, workspace)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
@@ -388,10 +423,7 @@ class Spline:
         """(V[B,N], G[B,3,N], H[B,6,N]) with H = Cartesian xx, xy, xz, yy, yz, zz."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, H = out if out is not None else self.alloc_vgh(B)
-        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (H, (B, 6, self.norb))):
-            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
-                raise ValueError("output tensor has wrong shape/dtype/device")
+        V, G, H = self._vgh_out(out, B)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
             check(lib().spline_eval_vgh(self._h, ctypes.c_void_p(pos.data_ptr()), B, ctypes.c_void_p(V.data_ptr()),
@@ -402,10 +434,7 @@ class Spline:
         """eval_vgh in locality order (same results bit for bit)."""
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, H = out if out is not None else self.alloc_vgh(B)
-        for t, shp in ((V, (B, self.norb)), (G, (B, 3, self.norb)), (H, (B, 6, self.norb))):
-            if tuple(t.shape) != shp or t.dtype != self.out_dtype or not t.is_contiguous() or t.device != self.device:
-                raise ValueError("output tensor has wrong shape/dtype/device")
+        V, G, H = self._vgh_out(out, B)
         wp, wn = self._sorted_ws(B, workspace)
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
@@ -436,7 +465,7 @@ class Spline:
 
     def autotune_vgh(self, pos, reps: int = 5, out=None, stream=None):
         pos = self._pos(pos)
-        V, G, H = out if out is not None else self.alloc_vgh(pos.shape[0])
+        V, G, H = self._vgh_out(out, pos.shape[0])
         t = Tile()
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
@@ -520,7 +549,7 @@ class Spline:
     def autotune(self, pos, reps: int = 5, cache_path: str | None = None, out=None, stream=None):
         pos = self._pos(pos)
         B = pos.shape[0]
-        V, G, L = out if out is not None else self.alloc_outputs(B)
+        V, G, L = self._vgl_out(out, B)
         t = Tile()
         with self._torch.cuda.device(self.device):
             sp, _ = _stream_ptr(self._torch, self.device, stream)
@@ -557,7 +586,10 @@ class Plan:
             raise ValueError("need one positions tensor per table")
         self.splines = list(splines)
         self.positions = [s._pos(p) for s, p in zip(splines, positions)]
-        self.outs = list(outs) if outs is not None else [s.alloc_outputs(p.shape[0]) for s, p in zip(splines, positions)]
+        outs = [None] * n if outs is None else list(outs)
+        if len(outs) != n:
+            raise ValueError("need one (V, G, L) triple per table")
+        self.outs = [s._vgl_out(o, p.shape[0]) for s, p, o in zip(splines, self.positions, outs)]
         dev = splines[0].device
         Bs = (ctypes.c_int64 * n)(*[p.shape[0] for p in self.positions])
         nb = int((lib().spline_plan_workspace_bytes_sorted if self.sorted else lib().spline_plan_workspace_bytes)(n, Bs))
@@ -756,6 +788,14 @@ class SurrogateMLP:
         return (self._torch.empty((B, self.norb), **kw), self._torch.empty((B, 3, self.norb), **kw),
                 self._torch.empty((B, self.norb), **kw))
 
+    def _vgl(self, vgl, B, what):
+        """A caller's float32 (V, G, L) triple for B positions, checked."""
+        f32 = self._torch.float32
+        V, G, L = vgl
+        return (_need(V, f32, (B, self.norb), self.device, what + " V"),
+                _need(G, f32, (B, 3, self.norb), self.device, what + " G"),
+                _need(L, f32, (B, self.norb), self.device, what + " L"))
+
     @staticmethod
     def _p(t):
         return ctypes.c_void_p(t.data_ptr())
@@ -765,12 +805,14 @@ class SurrogateMLP:
         return self.buf.clone()
 
     def init_output(self, targets, stream=None):
-        V, G, L = targets
+        V, G, L = self._vgl(targets, targets[0].shape[0], "targets")
         check(_mlp_lib().spline_mlp_init_output(self._h, self._p(V), self._p(G), self._p(L), V.shape[0],
                                                 self._stream(stream)))
 
     def grad(self, pos, targets, stream=None):
+        pos = _need_pos(pos, self.device)
         B = pos.shape[0]
+        targets = self._vgl(targets, B, "targets")
         L_ = _mlp_lib()
         nb = L_.spline_mlp_train_workspace_bytes(self._h, B)
         ws = self._workspace("train", nb)
@@ -782,7 +824,11 @@ class SurrogateMLP:
         return g, loss
 
     def train_step(self, pos, targets, lr: float, loss_out=None, stream=None):
+        pos = _need_pos(pos, self.device)
         B = pos.shape[0]
+        targets = self._vgl(targets, B, "targets")
+        if loss_out is not None:
+            _need(loss_out, self._torch.float32, (1,), self.device, "loss_out")
         L_ = _mlp_lib()
         nb = L_.spline_mlp_train_workspace_bytes(self._h, B)
         ws = self._workspace("train", nb)
@@ -792,13 +838,15 @@ class SurrogateMLP:
                                        None if loss_out is None else self._p(loss_out), self._stream(stream)))
 
     def forward(self, pos, out=None, stream=None):
+        pos = _need_pos(pos, self.device)
         B = pos.shape[0]
-        V, G, L = out if out is not None else self._out(B)
+        V, G, L = self._vgl(out, B, "out") if out is not None else self._out(B)
         check(_mlp_lib().spline_mlp_forward(self._h, self._p(pos), B, self._p(V), self._p(G), self._p(L),
                                             self._stream(stream)))
         return V, G, L
 
     def build_error_map(self, judge, val_pos, bins_per_dim: int = 8, stream=None):
+        val_pos = _need_pos(val_pos, self.device, "val_pos")
         L_ = _mlp_lib()
         n = val_pos.shape[0]
         ws = self._workspace("errmap", L_.spline_mlp_errmap_workspace_bytes(self._h, n))
@@ -807,9 +855,10 @@ class SurrogateMLP:
 
     def eval_vgl(self, pos, fallback=None, tol: float = 1e-3, out=None, stream=None):
         """(V, G, L, n_fallback tensor) with routing of untrusted bins to `fallback`."""
+        pos = _need_pos(pos, self.device)
         B = pos.shape[0]
         L_ = _mlp_lib()
-        V, G, L = out if out is not None else self._out(B)
+        V, G, L = self._vgl(out, B, "out") if out is not None else self._out(B)
         ws = self._workspace("eval", L_.spline_mlp_eval_workspace_bytes(B))
         nf = self._torch.zeros(1, dtype=self._torch.int32, device=self.device)
         check(L_.spline_mlp_eval_vgl(self._h, None if fallback is None else fallback.handle, float(tol),
@@ -931,7 +980,8 @@ class Jastrow:
         t = self._torch
         R, ld, ws = self._R(R)
         count = self._slots(R, k, rnew, walkers)
-        out = out if out is not None else t.empty((count, 5), dtype=t.float32, device=self.device)
+        out = (_need(out, t.float32, (count, 5), self.device, "out") if out is not None
+               else t.empty((count, 5), dtype=t.float32, device=self.device))
         with t.cuda.device(self.device):
             sp, _ = _stream_ptr(t, self.device, stream)
             check(lib().jastrow_move(self._h, self._p(R), ld, ws, self._p(walkers), self._p(k), self._p(rnew), count,
@@ -944,8 +994,13 @@ class Jastrow:
         R, ld, ws = self._R(R)
         W_ = R.shape[0]
         kw = dict(dtype=t.float32, device=self.device)
-        J, G, L = out if out is not None else (t.empty(W_, **kw), t.empty((W_, 3, self.n_elec), **kw),
-                                               t.empty((W_, self.n_elec), **kw))
+        if out is not None:
+            J, G, L = out
+            J = _need(J, t.float32, (W_,), self.device, "J")
+            G = _need(G, t.float32, (W_, 3, self.n_elec), self.device, "G")
+            L = _need(L, t.float32, (W_, self.n_elec), self.device, "L")
+        else:
+            J, G, L = t.empty(W_, **kw), t.empty((W_, 3, self.n_elec), **kw), t.empty((W_, self.n_elec), **kw)
         with t.cuda.device(self.device):
             sp, _ = _stream_ptr(t, self.device, stream)
             check(lib().jastrow_evaluate(self._h, self._p(R), ld, ws, W_, self._p(J), self._p(G), self._p(L), sp))
@@ -1025,20 +1080,30 @@ class DelayedUpdate:
 
     def _slots(self, k, V, walkers):
         t = self._torch
+        if not (isinstance(k, t.Tensor) and k.dim() == 1):
+            raise ValueError("k must be a contiguous int32 [count] tensor")
         count = k.shape[0]
-        if not (isinstance(k, t.Tensor) and k.dtype == t.int32 and k.device == self.device and k.is_contiguous()):
-            raise ValueError("k must be a contiguous int32 tensor")
-        if not (isinstance(V, t.Tensor) and V.dtype == t.float32 and V.is_contiguous()
-                and tuple(V.shape) == (count, self.n)):
-            raise ValueError("V must be a contiguous float32 [count, n] tensor")
+        _need(k, t.int32, (count,), self.device, "k")
+        _need(V, t.float32, (count, self.n), self.device, "V")
         if walkers is not None:
-            if not (isinstance(walkers, t.Tensor) and walkers.dtype == t.int32 and walkers.is_contiguous()
-                    and tuple(walkers.shape) == (count,)):
-                raise ValueError("walkers must be a contiguous int32 [count] tensor")
+            _need(walkers, t.int32, (count,), self.device, "walkers")
             # indices are range-checked by the kernels (NaN ratio, skipped accept): no host sync here
         elif count > self.walkers:
             raise ValueError("more slots than walkers")
         return count
+
+    def _ratio_args(self, count, G, L, out):
+        """The optional derivative rows and the [count, 5] / [count] output."""
+        t = self._torch
+        if (G is None) != (L is None):
+            raise ValueError("give both G and L, or neither")
+        if G is not None:
+            _need(G, t.float32, (count, 3, self.n), self.device, "G")
+            _need(L, t.float32, (count, self.n), self.device, "L")
+        shape = (count, 5) if G is not None else (count,)
+        if out is None:
+            return t.empty(shape, dtype=t.float32, device=self.device)
+        return _need(out, t.float32, shape, self.device, "out")
 
     @staticmethod
     def _p(x):
@@ -1047,13 +1112,7 @@ class DelayedUpdate:
     def ratio(self, ainv, k, V, G=None, L=None, walkers=None, out=None, stream=None):
         t = self._torch
         count = self._slots(k, V, walkers)
-        if (G is None) != (L is None):
-            raise ValueError("give both G and L, or neither")
-        if G is not None and (tuple(G.shape) != (count, 3, self.n) or tuple(L.shape) != (count, self.n)
-                              or not G.is_contiguous() or not L.is_contiguous()):
-            raise ValueError("G [count, 3, n] and L [count, n] must be contiguous")
-        shape = (count, 5) if G is not None else (count,)
-        out = out if out is not None else t.empty(shape, dtype=t.float32, device=self.device)
+        out = self._ratio_args(count, G, L, out)
         with t.cuda.device(self.device):
             sp, _ = _stream_ptr(t, self.device, stream)
             check(lib().spline_dlu_ratio(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers), self._p(k),
@@ -1075,13 +1134,7 @@ class DelayedUpdate:
         count = self._slots(k, V, walkers)
         if self._slots(k_acc, V_acc, walkers) != count:
             raise ValueError("accepted and proposed slots differ in count")
-        if (G is None) != (L is None):
-            raise ValueError("give both G and L, or neither")
-        if G is not None and (tuple(G.shape) != (count, 3, self.n) or tuple(L.shape) != (count, self.n)
-                              or not G.is_contiguous() or not L.is_contiguous()):
-            raise ValueError("G [count, 3, n] and L [count, n] must be contiguous")
-        shape = (count, 5) if G is not None else (count,)
-        out = out if out is not None else t.empty(shape, dtype=t.float32, device=self.device)
+        out = self._ratio_args(count, G, L, out)
         with t.cuda.device(self.device):
             sp, _ = _stream_ptr(t, self.device, stream)
             check(lib().spline_dlu_accept_ratio(self._h, self._ainv(ainv), self.n * self.n, self._p(walkers),
