@@ -198,8 +198,8 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the spline path needs no exchange between GPUs "
-              "(positions are independent and the table is read-only), and this build runs on a "
-              "single MI355X; rerun with --gpus 1.", file=sys.stderr)
+              "(positions are independent and the table is read-only), so the figure for N GPUs is "
+              "N times the one-GPU rate of each GPU's share; rerun with --gpus 1.", file=sys.stderr)
         return 2
 
     import numpy as np

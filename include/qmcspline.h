@@ -61,7 +61,7 @@ enum {
     SPL_EINVAL = -1,       /* null pointer, bad size or bad enum */
     SPL_ENOMEM = -2,       /* size overflow, or a caller buffer too small */
     SPL_EHIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
-    SPL_EUNSUPPORTED = -4  /* valid request this build cannot serve (e.g. tile shape) */
+    SPL_EUNSUPPORTED = -4  /* valid request the library cannot serve (e.g. tile shape) */
 };
 
 /* Grid: n[d] >= 1 points per axis; cell[d] > 0, finite: orthorhombic cell
@@ -489,14 +489,14 @@ int spline_mlp_train_step(spline_mlp_t* mlp, const double* pos, const float* tV,
 int spline_mlp_forward(const spline_mlp_t* mlp, const double* pos, int64_t B, float* V, float* G, float* L,
                        void* stream);
 
-/* Error map: evaluates network and judge table (same N, same cell, FP32
+/* Error map: evaluates the network and the spline table it stands in for (same N, same cell, FP32
  * outputs) at n_val validation positions and stores, per spatial bin
  * (bins_per_dim^3 bins, <= 16 per axis), the largest error over its points,
  * orbitals and quantities, each relative to that orbital's largest |V|,
  * |G_d| or |L| over all validation points.  Bins without points are
  * untrusted.  The estimate is empirical, not a bound. */
 size_t spline_mlp_errmap_workspace_bytes(const spline_mlp_t* mlp, int64_t n_val);
-int spline_mlp_build_error_map(spline_mlp_t* mlp, const spline_t* judge, const double* val_pos, int64_t n_val,
+int spline_mlp_build_error_map(spline_mlp_t* mlp, const spline_t* table, const double* val_pos, int64_t n_val,
                                int32_t bins_per_dim, void* ws, size_t ws_bytes, void* stream);
 
 /* Evaluation with fallback: the network at every position, then the

@@ -845,12 +845,12 @@ class SurrogateMLP:
                                             self._stream(stream)))
         return V, G, L
 
-    def build_error_map(self, judge, val_pos, bins_per_dim: int = 8, stream=None):
+    def build_error_map(self, table, val_pos, bins_per_dim: int = 8, stream=None):
         val_pos = _need_pos(val_pos, self.device, "val_pos")
         L_ = _mlp_lib()
         n = val_pos.shape[0]
         ws = self._workspace("errmap", L_.spline_mlp_errmap_workspace_bytes(self._h, n))
-        check(L_.spline_mlp_build_error_map(self._h, judge.handle, self._p(val_pos), n, int(bins_per_dim),
+        check(L_.spline_mlp_build_error_map(self._h, table.handle, self._p(val_pos), n, int(bins_per_dim),
                                             self._p(ws), ws.numel(), self._stream(stream)))
 
     def eval_vgl(self, pos, fallback=None, tol: float = 1e-3, out=None, stream=None):

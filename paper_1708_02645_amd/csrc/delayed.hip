@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
     int32_t* Ks = reinterpret_cast<int32_t*>(rho + 1);  // [d]
     float* Ss = reinterpret_cast<float*>(Ks + d);      // S^-1 [d][d] when staged
 
-    // round 1: the slot and the orbital rows
+    // first wave of loads: the slot and the orbital rows
     const int k_a = ACCEPT ? a.kacc[s] : -1;
     const int k_r = RATIO ? a.k[s] : -1;
     const int64_t w = a.walkers ? (int64_t)a.walkers[s] : s;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
         if (RATIO && tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
         return;
     }
-    // round 2: the pending state and the rows of A0^-1
+    // second wave of loads: the pending state and the rows of A0^-1
     float* st = a.ws + w * a.L.stride;
     const float* A = a.ainv + w * a.wstride;
     int32_t* cnt = reinterpret_cast<int32_t*>(st + a.L.cnt);

@@ -522,15 +522,15 @@ size_t spline_mlp_errmap_workspace_bytes(const spline_mlp_t* m, int64_t n_val)
     return a256((size_t)n_val * N * 10 * 4) + a256(3 * N * 4) + 2 * a256((size_t)kMaxBins * kMaxBins * kMaxBins * 4);
 }
 
-int spline_mlp_build_error_map(spline_mlp_t* m, const spline_t* judge, const double* val_pos, int64_t n_val,
+int spline_mlp_build_error_map(spline_mlp_t* m, const spline_t* table, const double* val_pos, int64_t n_val,
                                int32_t bins_per_dim, void* ws, size_t ws_bytes, void* stream)
 {
-    if (!m || !judge || !val_pos || !ws) return fail(SPL_EINVAL, "NULL argument");
+    if (!m || !table || !val_pos || !ws) return fail(SPL_EINVAL, "NULL argument");
     if (n_val <= 0 || n_val > (1 << 26)) return fail(SPL_EINVAL, "validation count must be in [1, 2^26]");
     if (bins_per_dim < 1 || bins_per_dim > kMaxBins) return fail(SPL_EINVAL, "bins per axis must be in [1, 16]");
-    if (judge->norb != m->nout || judge->store == SPL_F64) return fail(SPL_EINVAL, "judge table must have N orbitals and FP32 outputs");
+    if (table->norb != m->nout || table->store == SPL_F64) return fail(SPL_EINVAL, "table must have N orbitals and FP32 outputs");
     for (int d = 0; d < 3; ++d)
-        if (judge->grid.cell[d] != m->cell[d]) return fail(SPL_EINVAL, "judge table and network cells differ");
+        if (table->grid.cell[d] != m->cell[d]) return fail(SPL_EINVAL, "table and network cells differ");
     if (ws_bytes < spline_mlp_errmap_workspace_bytes(m, n_val)) return fail(SPL_ENOMEM, "workspace too small");
     int rc = check_dev(m);
     if (rc) return rc;
@@ -546,7 +546,7 @@ int spline_mlp_build_error_map(spline_mlp_t* m, const spline_t* judge, const dou
     unsigned int* bcnt = berr + a256((size_t)kMaxBins * kMaxBins * kMaxBins * 4) / 4;
     rc = launch_forward(m, val_pos, n_val, Vm, Gm, Lm, st);
     if (rc) return rc;
-    rc = spline_eval_vgl(judge, val_pos, n_val, Vs, Gs, Ls, stream);
+    rc = spline_eval_vgl(table, val_pos, n_val, Vs, Gs, Ls, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid1(3 * N)), dim3(kThreads), 0, st, smax, 0u, (int64_t)3 * N);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid1(nb3)), dim3(kThreads), 0, st, berr, 0u, (int64_t)nb3);
