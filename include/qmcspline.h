@@ -168,8 +168,8 @@ int spline_eval_vgh_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
                            void* workspace_dev, size_t workspace_bytes, void* stream);
 /* The fused determinant ratio in locality order: arguments and errors of
  * spline_eval_ratio_vgl / spline_eval_ratio_v, plus the workspace of
- * spline_eval_vgl_sorted.  Uses the sorted tile shape (the value tile for
- * the ratio alone).  The order of the ratio's partial sums depends on the
+ * spline_eval_vgl_sorted.  Uses the sorted tile shape (the sorted value
+ * tile for the ratio alone).  The order of the ratio's partial sums depends on the
  * tile shape, so the results equal those of the plain entry point run with
  * the same shape, bit for bit (and differ from other shapes by rounding). */
 int spline_eval_ratio_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
@@ -178,12 +178,17 @@ int spline_eval_ratio_vgl_sorted(const spline_t* s, const double* pos_dev, int64
 int spline_eval_ratio_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
                                int64_t ld, const int32_t* rows_dev, void* R, void* workspace_dev,
                                size_t workspace_bytes, void* stream);
-/* The locality-ordered VGL path has its own tile shape (initially the VGL
- * shape; the value-only path uses the value tile).  spline_autotune_sorted
- * works as spline_autotune over that path (bitwise cross-check of every
- * candidate, cache key with " sorted" appended) and selects the fastest. */
+/* The locality-ordered paths have their own tile shapes: one for VGL and
+ * one for value only and the value ratio (initially the plain VGL and value
+ * shapes).  spline_set_sorted_tile sets both (the value shape when that
+ * shape has a value-only kernel); spline_get_sorted_value_tile reads the
+ * value shape.  spline_autotune_sorted works as spline_autotune over these
+ * paths: it tunes both shapes (bitwise cross-check of every candidate; the
+ * candidates also include 8 positions per workgroup), with cache keys
+ * "<key> sorted" and "<key> sorted V", and returns the VGL shape. */
 int spline_set_sorted_tile(spline_t* s, const spline_tile* tile);
 int spline_get_sorted_tile(const spline_t* s, spline_tile* tile);
+int spline_get_sorted_value_tile(const spline_t* s, spline_tile* tile);
 int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
                            void* workspace_dev, size_t workspace_bytes, int32_t reps, const char* cache_path,
                            void* stream, spline_tile* chosen);

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/qmcspline.h"
 
@@ -135,6 +137,13 @@ int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, vo
                  hipStream_t st, spline_tile* chosen);
 // Tile validation and the tuning cache (spline_host.cpp).
 int check_tile(const spline_s* s, const spline_tile* t, bool vgl);
+// Times every candidate shape (run(t) launches one evaluation with shape t
+// writing V, and G, L for VGL) and returns the fastest in *best; every
+// candidate must reproduce the first one's outputs on the first positions
+// bit for bit.  Candidates without a value-only kernel are skipped for !vgl.
+int tune_kind(const spline_s* s, bool vgl, const std::vector<spline_tile>& cands, int64_t B, void* V, void* G,
+              void* L, int32_t reps, hipStream_t st, const std::function<int(const spline_tile&)>& run,
+              spline_tile* best);
 std::string tune_key(const spline_s* s, int64_t B);
 bool cache_lookup(const char* path, const std::string& key, spline_tile* t);
 
@@ -152,6 +161,7 @@ struct spline_s {
     spline_tile vtile;     // current value-only tile shape
     spline_tile htile;     // current shape of the VGH family (also general-cell VGL)
     spline_tile stile;     // current VGL tile shape of the locality-ordered path
+    spline_tile svtile;    // its value-only (and value-ratio) tile shape
     int general;           // 1 once a general lattice is set
     double lat[9];         // lattice vectors as rows (general cells)
     double ilat[9];        // its inverse

@@ -238,7 +238,7 @@ static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* 
         if (!vgl) return fail(SPL_EUNSUPPORTED, "value-only evaluation is built for orthorhombic cells");
         return sorted_vgh(s, false, pos, B, V, G, L, ws, st);
     }
-    return sorted_run(s, vgl ? s->stile : s->vtile, vgl, pos, B, V, G, L, ws, st);
+    return sorted_run(s, vgl ? s->stile : s->svtile, vgl, pos, B, V, G, L, ws, st);
 }
 
 }  // namespace qs
@@ -267,7 +267,7 @@ int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, vo
 
 // Determinant ratio in locality order: as spline_eval_ratio_vgl / _v (the
 // row of A^-1 for position b is still ainv + (rows ? rows[b] : b) * ld), with
-// the sorted tile shape (the value tile for the ratio alone).  The ratio's
+// the sorted tile shape (the sorted value tile for the ratio alone).  The ratio's
 // partial sums follow the tile shape, so the results equal the plain entry
 // point's under the same shape.  Positions per workgroup are halved until
 // the per-tile partial sums fit in LDS.
@@ -283,7 +283,7 @@ static int sorted_ratio(const spline_s* s, const double* pos, int64_t B, const v
     const uintptr_t eb = s->store == SPL_F64 ? 8 : 4;
     if ((uintptr_t)ainv % eb || (uintptr_t)D % eb)
         return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
-    spline_tile t = vgl ? s->stile : s->vtile;
+    spline_tile t = vgl ? s->stile : s->svtile;
     const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
     if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");
     const int64_t tiles = tiles_of(s, t);
@@ -331,6 +331,7 @@ int spline_set_sorted_tile(spline_t* s, const spline_tile* tile)
     const int rc = check_tile(s, tile, true);
     if (rc) return rc;
     s->stile = *tile;
+    if (find_variant(s->store, tile->cw, tile->nch, tile->lpp, false)) s->svtile = *tile;
     return SPL_OK;
 }
 
@@ -341,9 +342,11 @@ int spline_get_sorted_tile(const spline_t* s, spline_tile* tile)
     return SPL_OK;
 }
 
-// As spline_autotune, over the locality-ordered VGL path: every candidate's
-// outputs on the first positions must equal the first candidate's bit for
-// bit; cache lines "<key> sorted|cw nch lpp pb".
+// As spline_autotune, over the locality-ordered paths: the VGL shape and the
+// value-only shape (also used by the value ratio) are tuned separately, each
+// candidate's outputs on the first positions must equal the first
+// candidate's bit for bit; cache lines "<key> sorted|cw nch lpp pb" and
+// "<key> sorted V|cw nch lpp pb".
 int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
                            void* workspace_dev, size_t workspace_bytes, int32_t reps, const char* cache_path,
                            void* stream, spline_tile* chosen)
@@ -354,75 +357,49 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
     if (s->general) return fail(SPL_EUNSUPPORTED, "general cells use the VGH-family tile (spline_autotune_vgh)");
     if (reps < 1) reps = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const std::string key = tune_key(s, B) + " sorted";
-    spline_tile best_t{};
-    if (cache_path && cache_lookup(cache_path, key, &best_t) && check_tile(s, &best_t, true) == SPL_OK) {
-        s->stile = best_t;
-        if (chosen) *chosen = best_t;
-        return SPL_OK;
-    }
-    int32_t n = 0;
-    rc = spline_tile_candidates(s, nullptr, 0, &n);
-    if (rc) return rc;
-    std::vector<spline_tile> cands(n);
-    spline_tile_candidates(s, cands.data(), n, &n);
-    // Shorter chunks too: fewer positions in flight per XCD keep more of
-    // their shared rows in its L2.
-    for (int32_t i = 0; i < n; ++i)
-        if (cands[i].pb == 16) cands.push_back(spline_tile{cands[i].cw, cands[i].nch, cands[i].lpp, 8});
-    n = (int32_t)cands.size();
-    if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
-    const int64_t Bc = std::min<int64_t>(B, 512);
-    const size_t nv = (size_t)Bc * s->norb * (s->store == SPL_F64 ? 8 : 4);
-    std::vector<unsigned char> ref, cur(5 * nv);
-    hipEvent_t e0, e1;
-    QS_HIP(hipEventCreate(&e0));
-    QS_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    best_t = cands[0];
-    for (int i = 0; i < n && rc == SPL_OK; ++i) {
-        const spline_tile t = cands[i];
-        rc = sorted_run(s, t, true, pos_dev, B, V, G, L, workspace_dev, st);
-        if (rc) break;
-        if (hipMemcpyAsync(cur.data(), V, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(cur.data() + nv, G, 3 * nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(cur.data() + 4 * nv, L, nv, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            rc = fail(SPL_EHIP, "autotune: copy of outputs failed");
-            break;
+    const std::string key = tune_key(s, B) + " sorted", vkey = key + " V";
+    spline_tile tv{}, tn{};
+    const bool have_v = cache_path && cache_lookup(cache_path, key, &tv) && check_tile(s, &tv, true) == SPL_OK;
+    const bool have_n = cache_path && cache_lookup(cache_path, vkey, &tn) && check_tile(s, &tn, false) == SPL_OK;
+    if (!have_v || !have_n) {
+        int32_t n = 0;
+        rc = spline_tile_candidates(s, nullptr, 0, &n);
+        if (rc) return rc;
+        std::vector<spline_tile> cands(n);
+        spline_tile_candidates(s, cands.data(), n, &n);
+        // Shorter chunks too: fewer positions in flight per XCD keep more of
+        // their shared rows in its L2.
+        for (int32_t i = 0; i < n; ++i)
+            if (cands[i].pb == 16) cands.push_back(spline_tile{cands[i].cw, cands[i].nch, cands[i].lpp, 8});
+        if (cands.empty()) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
+        if (!have_v) {
+            rc = tune_kind(s, true, cands, B, V, G, L, reps, st, [&](const spline_tile& t) {
+                return sorted_run(s, t, true, pos_dev, B, V, G, L, workspace_dev, st);
+            }, &tv);
+            if (rc) return rc;
         }
-        if (ref.empty()) {
-            ref = cur;
-        } else if (std::memcmp(ref.data(), cur.data(), ref.size()) != 0) {
-            rc = fail(SPL_EUNSUPPORTED, "autotune: a tile shape differs bitwise from the first candidate");
-            break;
-        }
-        if (hipEventRecord(e0, st) != hipSuccess) {
-            rc = fail(SPL_EHIP, "event record");
-            break;
-        }
-        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = sorted_run(s, t, true, pos_dev, B, V, G, L, workspace_dev, st);
-        if (rc) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = fail(SPL_EHIP, "autotune: event timing failed");
-            break;
-        }
-        if (ms < best) {
-            best = ms;
-            best_t = t;
+        if (!have_n) {
+            rc = tune_kind(s, false, cands, B, V, G, L, reps, st, [&](const spline_tile& t) {
+                return sorted_run(s, t, false, pos_dev, B, V, nullptr, nullptr, workspace_dev, st);
+            }, &tn);
+            if (rc) return rc;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc) return rc;
-    s->stile = best_t;
-    if (chosen) *chosen = best_t;
+    s->stile = tv;
+    s->svtile = tn;
+    if (chosen) *chosen = tv;
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        if (f) f << key << "|" << best_t.cw << " " << best_t.nch << " " << best_t.lpp << " " << best_t.pb << "\n";
+        if (f && !have_v) f << key << "|" << tv.cw << " " << tv.nch << " " << tv.lpp << " " << tv.pb << "\n";
+        if (f && !have_n) f << vkey << "|" << tn.cw << " " << tn.nch << " " << tn.lpp << " " << tn.pb << "\n";
     }
+    return SPL_OK;
+}
+
+int spline_get_sorted_value_tile(const spline_t* s, spline_tile* tile)
+{
+    if (!s || !tile) return fail(SPL_EINVAL, "NULL argument");
+    *tile = s->svtile;
     return SPL_OK;
 }
 

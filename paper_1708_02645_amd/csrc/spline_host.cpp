@@ -417,6 +417,7 @@ int spline_create(const spline_grid* grid, int32_t n_orb, const double* coefs_ho
     s->vtile = default_tile(s, false);
     s->htile = default_vgh_tile(s);
     s->stile = s->tile;
+    s->svtile = s->vtile;
     s->general = 0;
     if (s->tile.cw == 0 || s->vtile.cw == 0 || s->htile.cw == 0) {
         delete s;
@@ -605,12 +606,11 @@ bool cache_lookup(const char* path, const std::string& key, spline_tile* t)
 
 namespace qs {
 
-// Times every candidate shape for VGL (vgl) or value-only evaluation and
-// returns the fastest in *best.  Every candidate must reproduce the first
-// one's outputs bit for bit (the accumulation order does not depend on the
-// tile shape).
-static int tune_kind(spline_s* s, bool vgl, const std::vector<spline_tile>& cands, const double* pos, int64_t B,
-                     void* V, void* G, void* L, int32_t reps, hipStream_t st, spline_tile* best_t)
+// The accumulation order does not depend on the tile shape, so every
+// candidate must give the first one's outputs bit for bit.
+int tune_kind(const spline_s* s, bool vgl, const std::vector<spline_tile>& cands, int64_t B, void* V, void* G,
+              void* L, int32_t reps, hipStream_t st, const std::function<int(const spline_tile&)>& run,
+              spline_tile* best_t)
 {
     const int64_t Bc = std::min<int64_t>(B, 512);
     const size_t ob = s->store == SPL_F64 ? 8 : 4;
@@ -626,7 +626,7 @@ static int tune_kind(spline_s* s, bool vgl, const std::vector<spline_tile>& cand
     for (size_t i = 0; i < cands.size(); ++i) {
         spline_tile t = cands[i];
         if (!vgl && !find_variant(s->store, t.cw, t.nch, t.lpp, false)) continue;
-        rc = run_eval(s, t, vgl, pos, B, V, G, L, st);
+        rc = run(t);
         if (rc) break;
         bool copied = hipMemcpyAsync(cur.data(), V, nv, hipMemcpyDeviceToHost, st) == hipSuccess;
         if (vgl)
@@ -646,7 +646,7 @@ static int tune_kind(spline_s* s, bool vgl, const std::vector<spline_tile>& cand
             break;
         }
         if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SPL_EHIP, "event record"); break; }
-        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = run_eval(s, t, vgl, pos, B, V, G, L, st);
+        for (int r = 0; r < reps && rc == SPL_OK; ++r) rc = run(t);
         if (rc) break;
         float ms = 0.f;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -693,11 +693,13 @@ extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, vo
     spline_tile_candidates(s, cands.data(), n, &n);
     if (n == 0) return fail(SPL_EUNSUPPORTED, "no candidate tile shapes");
     if (!have_v) {
-        rc = tune_kind(s, true, cands, pos_dev, B, V, G, L, reps, st, &tv);
+        rc = tune_kind(s, true, cands, B, V, G, L, reps, st,
+                       [&](const spline_tile& t) { return run_eval(s, t, true, pos_dev, B, V, G, L, st); }, &tv);
         if (rc) return rc;
     }
     if (!have_n) {
-        rc = tune_kind(s, false, cands, pos_dev, B, V, G, L, reps, st, &tn);
+        rc = tune_kind(s, false, cands, B, V, G, L, reps, st,
+                       [&](const spline_tile& t) { return run_eval(s, t, false, pos_dev, B, V, G, L, st); }, &tn);
         if (rc) return rc;
     }
     s->tile = tv;

@@ -189,7 +189,10 @@ def test_ratio_small_equal(torch, q, dtype):
     pos = torch.from_numpy(W.make_positions(1)).cuda()
     ainv = torch.from_numpy(rng.normal(size=(B, N)) / np.sqrt(N)).to(s.out_dtype).cuda()
     rows = torch.from_numpy(rng.integers(0, B, B).astype(np.int32)).cuda()
-    s.set_sorted_tile(s.get_tile())  # the ratio's sums follow the tile shape: compare under one shape
+    t = s.get_tile()
+    s.set_tile(t)  # the ratio's sums follow the tile shape: compare under one shape (VGL and value)
+    s.set_sorted_tile(t)
+    assert s.get_value_tile() == s.get_sorted_value_tile() == tuple(t)
     for r in (None, rows):
         _say("case sorted ratio", dtype, r is None)
         _same(torch, (s.eval_ratio_vgl_sorted(pos, ainv, rows=r),), (s.eval_ratio_vgl(pos, ainv, rows=r),))
@@ -208,8 +211,11 @@ def test_ratio_full_size_equal(torch, q):
     s.autotune(pos, reps=2, cache_path=os.path.join(os.path.dirname(q.__file__), "tune_cache.txt"))
     ainv = torch.from_numpy(W.make_inverse_rows(3, pos_np.shape[0], N)).cuda()
     st = s.autotune_sorted(pos, reps=1, cache_path=os.path.join(os.path.dirname(q.__file__), "tune_cache.txt"))
-    _say("case sorted ratio full", st)
+    sv = s.get_sorted_value_tile()
+    _say("case sorted ratio full", st, sv)
     D = s.eval_ratio_vgl_sorted(pos, ainv)
-    _same(torch, (s.eval_ratio_v_sorted(pos, ainv),), (s.eval_ratio_v(pos, ainv),))
+    R = s.eval_ratio_v_sorted(pos, ainv)
+    s.set_tile(sv)  # the plain value path under the sorted value shape
+    _same(torch, (R,), (s.eval_ratio_v(pos, ainv),))
     s.set_tile(st)  # the plain path under the sorted shape
     _same(torch, (D,), (s.eval_ratio_vgl(pos, ainv),))
