@@ -73,42 +73,24 @@ __device__ inline float dwave_sum(float x)
     return x;
 }
 
-// The dot products of a ratio or an accept: x[q] = a . q_q, t[i] = a . phi_i,
-// y[i][q] = a_{K_i} . q_q.  Each wave takes eight dots at a time and loads
-// four 64-column steps of all eight before using any, so a dot costs about
+// `total` dot products p1 . p2 -> *dst, the pointers of dot e from
+// job(e, p1, p2, dst).  Each wave takes eight dots at a time and loads four
+// 64-column steps of all eight before using any, so a dot costs about
 // n / 256 memory round trips; every dot is accumulated over m = lane,
 // lane + 64, ... in that order and reduced by a butterfly, the same order
-// whichever wave and slot takes it.
-template <int NQ>
-__device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const int32_t* K,
-                                const float* as, const float* qs, float* x, float* t, float* y)
+// whichever wave and slot takes it, and whichever other dots share the pass.
+template <typename Job>
+__device__ inline void dlu_dot_set(int n, int total, Job job)
 {
     constexpr int U = 8, R = 4;
-    const int n = a.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float* Phi = st + a.L.phi;
-    const int total = NQ + j + j * NQ;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e0 = wave * U; e0 < total; e0 += (kDThreads / 64) * U) {
         const float* p1[U];
         const float* p2[U];
         float* dst[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u < total ? e0 + u : total - 1;  // a repeated last dot is computed, not stored twice
-            if (e < NQ) {
-                p1[u] = as;
-                p2[u] = qs + e * n;
-                dst[u] = x + e;
-            } else if (e < NQ + j) {
-                p1[u] = as;
-                p2[u] = Phi + (int64_t)(e - NQ) * n;
-                dst[u] = t + (e - NQ);
-            } else {
-                const int f = e - NQ - j, i = f / NQ, q = f - i * NQ;
-                p1[u] = A + (int64_t)K[i] * n;
-                p2[u] = qs + q * n;
-                dst[u] = y + i * NQ + q;
-            }
-        }
+        for (int u = 0; u < U; ++u)
+            job(e0 + u < total ? e0 + u : total - 1, p1[u], p2[u], dst[u]);  // a repeated last dot is not stored twice
         float s[U] = {};
         for (int m0 = lane; m0 < n; m0 += 64 * R) {
             float v1[U][R], v2[U][R];
@@ -133,6 +115,56 @@ __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* s
             if (lane == 0 && e0 + u < total) *dst[u] = r;
         }
     }
+}
+
+// The dots of a ratio or an accept against j pending moves: x[q] = a . q_q,
+// t[i] = a . phi_i, y[i][q] = a_{K_i} . q_q (dot e of NQ + j + j NQ).
+template <int NQ>
+__device__ inline void dlu_dot_job(int e, int n, int j, const float* A, const float* Phi, const int32_t* K,
+                                   const float* as, const float* qs, float* x, float* t, float* y, const float*& p1,
+                                   const float*& p2, float*& dst)
+{
+    if (e < NQ) {
+        p1 = as;
+        p2 = qs + e * n;
+        dst = x + e;
+    } else if (e < NQ + j) {
+        p1 = as;
+        p2 = Phi + (int64_t)(e - NQ) * n;
+        dst = t + (e - NQ);
+    } else {
+        const int f = e - NQ - j, i = f / NQ, q = f - i * NQ;
+        p1 = A + (int64_t)K[i] * n;
+        p2 = qs + q * n;
+        dst = y + i * NQ + q;
+    }
+}
+
+template <int NQ>
+__device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const int32_t* K,
+                                const float* as, const float* qs, float* x, float* t, float* y)
+{
+    const int n = a.n;
+    const float* Phi = st + a.L.phi;
+    dlu_dot_set(n, NQ + j + j * NQ, [&](int e, const float*& p1, const float*& p2, float*& dst) {
+        dlu_dot_job<NQ>(e, n, j, A, Phi, K, as, qs, x, t, y, p1, p2, dst);
+    });
+}
+
+// An accept's dots (NQ = 1) and a ratio's dots (NQ) against the same j
+// pending moves in one pass: the two sets read the same rows of Phi and of
+// A0^-1, and each dot is formed exactly as in its own pass.
+template <int NQ>
+__device__ inline void dlu_dots_both(const DluArgs& a, const float* A, const float* st, int j, const int32_t* K,
+                                     const float* aa, const float* qa, float* xa, float* ta, float* ya,
+                                     const float* ar, const float* qs, float* x, float* t, float* y)
+{
+    const int n = a.n, ta_total = 1 + 2 * j;
+    const float* Phi = st + a.L.phi;
+    dlu_dot_set(n, ta_total + NQ + j + j * NQ, [&](int e, const float*& p1, const float*& p2, float*& dst) {
+        if (e < ta_total) dlu_dot_job<1>(e, n, j, A, Phi, K, aa, qa, xa, ta, ya, p1, p2, dst);
+        else dlu_dot_job<NQ>(e - ta_total, n, j, A, Phi, K, ar, qs, x, t, y, p1, p2, dst);
+    });
 }
 
 // rows[r][m] = src[r][m] for r < NR, m < n: every load of a thread is issued
@@ -176,7 +208,8 @@ __device__ inline void dlu_lds_dots(const float* const* p1, const float* const* 
 // against the pending moves, the one just accepted included.  Memory is
 // read in two rounds: the slot and the orbital rows first (they depend on
 // the slot alone), then the pending count, electrons, S^-1 and the rows k of
-// A0^-1.  The move accepted here enters the ratio from LDS (its phi and its
+// A0^-1; then one pass of dot products over the pending rows serves both
+// the accept and the ratio.  The move accepted here enters the ratio from LDS (its phi and its
 // row of A0^-1), in the order of the dot products of a separate ratio call,
 // so a fused step equals an accept followed by a ratio bit for bit.
 // ACCEPT alone is spline_dlu_accept, RATIO alone spline_dlu_ratio.  A fused
@@ -251,8 +284,12 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
     __syncthreads();
 
     int jr = j;  // pending moves the ratio sees
-    if (acc_ok && j < d) {  // the host keeps accepts between flushes <= d
-        dlu_dots<1>(a, A, st, j, Ks, aa, qa, xa, ta, ya);
+    // Both steps: the ratio's dots against the moves pending before this step
+    // do not depend on the accept, so they share its pass over the rows.
+    const bool both = acc_ok && j < d && rat_ok;  // the host keeps accepts between flushes <= d
+    if (both) dlu_dots_both<NQ>(a, A, st, j, Ks, aa, qa, xa, ta, ya, ar, qs, x, t, y);
+    if (acc_ok && j < d) {
+        if (!both) dlu_dots<1>(a, A, st, j, Ks, aa, qa, xa, ta, ya);
         __syncthreads();
         if (tid < j) {
             float v = 0.f;
@@ -298,7 +335,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
             if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
             return;
         }
-        dlu_dots<NQ>(a, A, st, j, Ks, ar, qs, x, t, y);  // x, and the moves pending before this step
+        if (!both) dlu_dots<NQ>(a, A, st, j, Ks, ar, qs, x, t, y);  // x, and the moves pending before this step
         if (jr > j) {  // the move accepted above, from LDS: t_j = a_k . phi_j, y_j = a_{k_j} . q
             const float* p1[NQ + 1];
             const float* p2[NQ + 1];
