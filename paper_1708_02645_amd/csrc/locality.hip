@@ -222,10 +222,14 @@ static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const d
 static int sorted_vgh(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
                       void* ws, hipStream_t st)
 {
+    // At most 8 positions per workgroup: fewer positions in flight per XCD
+    // keep more of their shared rows in its L2 (the VGH tile is tuned on the
+    // plain path, where this does not matter).
+    const int pb = std::min(s->htile.pb, 8);
     const int32_t* perm = nullptr;
-    int rc = sort_positions(s, pos, B, s->htile.pb, ws, st, &perm);
+    int rc = sort_positions(s, pos, B, pb, ws, st, &perm);
     if (rc) return rc;
-    return vgh_launch_indexed(s, hessian, pos, B, V, G, H, perm, st);
+    return vgh_launch_indexed(s, hessian, pos, B, V, G, H, perm, st, pb);
 }
 
 static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, void* ws,

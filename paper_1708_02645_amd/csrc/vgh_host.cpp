@@ -183,9 +183,11 @@ int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* 
 // The VGH family (Hessian, or the general-cell Laplacian) through an index
 // list, with the handle's VGH-family tile (locality-ordered evaluation).
 int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
-                       const int32_t* idx, hipStream_t st)
+                       const int32_t* idx, hipStream_t st, int pb)
 {
-    return vgh_launch(s, s->htile, hessian ? VGH_OUT_H : VGH_OUT_L, pos, B, V, G, H, st, idx);
+    spline_tile t = s->htile;
+    if (pb > 0) t.pb = pb;
+    return vgh_launch(s, t, hessian ? VGH_OUT_H : VGH_OUT_L, pos, B, V, G, H, st, idx);
 }
 
 static int check_outputs(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* H)
