@@ -74,15 +74,15 @@ __device__ inline float dwave_sum(float x)
 }
 
 // `total` dot products p1 . p2 -> *dst, the pointers of dot e from
-// job(e, p1, p2, dst).  Each wave takes eight dots at a time and loads four
+// job(e, p1, p2, dst).  Each wave takes eight dots at a time and loads R
 // 64-column steps of all eight before using any, so a dot costs about
-// n / 256 memory round trips; every dot is accumulated over m = lane,
+// n / (64 R) memory round trips; every dot is accumulated over m = lane,
 // lane + 64, ... in that order and reduced by a butterfly, the same order
 // whichever wave and slot takes it, and whichever other dots share the pass.
-template <typename Job>
+template <int R, typename Job>
 __device__ inline void dlu_dot_set(int n, int total, Job job)
 {
-    constexpr int U = 8, R = 4;
+    constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e0 = wave * U; e0 < total; e0 += (kDThreads / 64) * U) {
         const float* p1[U];
@@ -140,13 +140,17 @@ __device__ inline void dlu_dot_job(int e, int n, int j, const float* A, const fl
     }
 }
 
+// Load steps per round: six (a 384-column dot in one round) where the
+// registers allow it; the load batching does not change any dot's order.
+template <int NQ> constexpr int dlu_rsteps() { return NQ == 1 ? 6 : 4; }
+
 template <int NQ>
 __device__ inline void dlu_dots(const DluArgs& a, const float* A, const float* st, int j, const int32_t* K,
                                 const float* as, const float* qs, float* x, float* t, float* y)
 {
     const int n = a.n;
     const float* Phi = st + a.L.phi;
-    dlu_dot_set(n, NQ + j + j * NQ, [&](int e, const float*& p1, const float*& p2, float*& dst) {
+    dlu_dot_set<dlu_rsteps<NQ>()>(n, NQ + j + j * NQ, [&](int e, const float*& p1, const float*& p2, float*& dst) {
         dlu_dot_job<NQ>(e, n, j, A, Phi, K, as, qs, x, t, y, p1, p2, dst);
     });
 }
@@ -161,7 +165,8 @@ __device__ inline void dlu_dots_both(const DluArgs& a, const float* A, const flo
 {
     const int n = a.n, ta_total = 1 + 2 * j;
     const float* Phi = st + a.L.phi;
-    dlu_dot_set(n, ta_total + NQ + j + j * NQ, [&](int e, const float*& p1, const float*& p2, float*& dst) {
+    dlu_dot_set<dlu_rsteps<NQ>()>(n, ta_total + NQ + j + j * NQ,
+                                  [&](int e, const float*& p1, const float*& p2, float*& dst) {
         if (e < ta_total) dlu_dot_job<1>(e, n, j, A, Phi, K, aa, qa, xa, ta, ya, p1, p2, dst);
         else dlu_dot_job<NQ>(e - ta_total, n, j, A, Phi, K, ar, qs, x, t, y, p1, p2, dst);
     });
