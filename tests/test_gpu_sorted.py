@@ -173,7 +173,10 @@ def test_full_size_equal(torch, q, dtype):
     _say("case sorted full", dtype, pos.shape, s.get_tile())
     _check_equal(torch, s, pos)
     t = s.autotune_sorted(torch.from_numpy(pos).cuda(), reps=1)  # no cache: searches, cross-checks bitwise
-    _say("case sorted full tuned", dtype, t)
+    _say("case sorted full tuned", dtype, t, s.get_sorted_value_tile())
+    _check_equal(torch, s, pos)
+    t = s.autotune_sorted(torch.from_numpy(pos).cuda(), reps=1, cache_path=cache)  # the bench's shapes
+    _say("case sorted full, bench shapes", dtype, t, s.get_sorted_value_tile())
     _check_equal(torch, s, pos)
 
 
