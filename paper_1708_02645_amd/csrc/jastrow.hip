@@ -31,6 +31,7 @@ constexpr int kMaxSpecies = 16;
 constexpr int kMaxIntervals = 256;
 constexpr int kMaxIons = 1024;
 constexpr int kMaxElecEval = 2048;  // jastrow_evaluate keeps a walker in LDS
+constexpr int kJEvalMaxThreads = 1024;  // jastrow_evaluate: one thread per electron up to this
 
 struct JFun {
     float rcut, hinv;
@@ -250,7 +251,9 @@ struct EvalJArgs {
     float* L;
 };
 
-__global__ __launch_bounds__(kJThreads) void jastrow_eval_kernel(EvalJArgs a)
+// One workgroup per walker with one thread per electron (whole waves,
+// at most kJEvalMaxThreads), so every thread runs the same partner loops.
+__global__ __launch_bounds__(kJEvalMaxThreads) void jastrow_eval_kernel(EvalJArgs a)
 {
     extern __shared__ unsigned char lds[];
     JStage st;
@@ -259,16 +262,17 @@ __global__ __launch_bounds__(kJThreads) void jastrow_eval_kernel(EvalJArgs a)
     j_stage(a.j, lds, st);
     float4* p = reinterpret_cast<float4*>(lds + ((reinterpret_cast<uintptr_t>(st.isp + a.j.n_ion) -
                                                   reinterpret_cast<uintptr_t>(lds) + 15) & ~uintptr_t(15)));
-    __shared__ float red[kJThreads / 64];
+    __shared__ float red[kJEvalMaxThreads / 64];
+    const int nt = blockDim.x;
     const int64_t w = blockIdx.x;
     const float* Rx = a.R + w * a.wstride;
-    for (int i = threadIdx.x; i < N; i += kJThreads) p[i] = make_float4(Rx[i], Rx[a.ld + i], Rx[2 * a.ld + i], 0.f);
+    for (int i = threadIdx.x; i < N; i += nt) p[i] = make_float4(Rx[i], Rx[a.ld + i], Rx[2 * a.ld + i], 0.f);
     __syncthreads();
     const float L0 = a.j.L[0], L1 = a.j.L[1], L2 = a.j.L[2];
     const float I0 = a.j.Linv[0], I1 = a.j.Linv[1], I2 = a.j.Linv[2];
     const int nup = a.j.n_up;
     float jpart = 0.f;
-    for (int i = threadIdx.x; i < N; i += kJThreads) {
+    for (int i = threadIdx.x; i < N; i += nt) {
         const float4 pi = p[i];
         const bool up = i < nup;
         const JFun fsame = st.fun[a.j.ns], fdiff = st.fun[a.j.ns + 1];
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(kJThreads) void jastrow_eval_kernel(EvalJArgs a)
     if (threadIdx.x == 0) {
         float t = red[0];
 #pragma unroll
-        for (int q = 1; q < kJThreads / 64; ++q) t += red[q];
+        for (int q = 1; q < nt / 64; ++q) t += red[q];
         a.J[w] = t;
     }
 }
@@ -560,7 +564,8 @@ int jastrow_evaluate(const jastrow_t* j, const float* R_dev, int64_t ld, int64_t
     EvalJArgs a{j_args(j), R_dev, ld, wstride, W, J, G, L};
     void* params[] = {&a};
     const size_t lds = stage_bytes(j) + 16 + 16 * (size_t)j->d.n_elec;
-    QS_HIP(hipLaunchKernel((const void*)&jastrow_eval_kernel, dim3((unsigned)W), dim3(kJThreads), params, lds,
+    const int threads = std::min(kJEvalMaxThreads, std::max(64, (j->d.n_elec + 63) / 64 * 64));
+    QS_HIP(hipLaunchKernel((const void*)&jastrow_eval_kernel, dim3((unsigned)W), dim3(threads), params, lds,
                            static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());
     return SPL_OK;
