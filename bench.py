@@ -586,20 +586,30 @@ def main() -> int:
                   torch.empty((nw, 3, NE), dtype=torch.float32, device=dev),
                   torch.empty((nw, NE), dtype=torch.float32, device=dev))
             ms_ev, _ = time_steps(torch, lambda: jas.evaluate(Rd, out=jo), args.steps, args.warmup)
-            pairs_ev = nw * NE * (NE - 1 + NI)
-            jforms["evaluate_%d_walkers" % nw] = {"ms_per_step": ms_ev, "pair_evals_per_s": pairs_ev / (ms_ev * 1e-3)}
+            pairs_ev = nw * NE * (NE - 1 + NI)  # pair terms of the definition (each e-e pair for both electrons)
+            ops_ev = nw * (NE * (NE - 1) // 2 * 69.0 + NE * NI * 66.0)
+            jforms["evaluate_%d_walkers" % nw] = {"ms_per_step": ms_ev, "pair_evals_per_s": pairs_ev / (ms_ev * 1e-3),
+                                                  "ops_per_step": ops_ev}
             del jo
         del Re, Rd, jout
     jforms["system"] = "%d electrons (%d up), %d ions of 2 species, unit cube, functors with 8 intervals, rcut 0.5" % (
         NE, jd["n_up"], NI)
-    # ALU roofline: FP32 operations of the definition per pair term (66 with
-    # derivatives, 41 for a value only; DESIGN lists them) against the VALU
-    # issue rate, 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (packed FP32 off).
+    # ALU roofline: FP32 operations of the definition against the VALU issue
+    # rate, 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (packed FP32 off).  A pair
+    # term with derivatives costs 66 operations, a value alone 41 (a move
+    # forms both, at the new and the old position); the full evaluation
+    # forms each electron pair once, 59 operations, and adds its terms to
+    # both electrons, 10 more: 69 per unordered pair, 66 per electron-ion pair.
     peak_ops = 256 * 4 * 16 * 2.4e9
     for key, v in jforms.items():
         if not isinstance(v, dict):
             continue
-        ops = 66.0 if key.startswith("evaluate") else (66.0 + 41.0) / 2
+        if key.startswith("evaluate"):
+            ops_s = v["ops_per_step"] / (v["ms_per_step"] * 1e-3)
+            v["roofline"] = {"bound": "alu", "ops_per_unordered_ee_pair": 69.0, "ops_per_ei_pair": 66.0,
+                             "achieved_Tops": ops_s / 1e12, "peak_Tops": peak_ops / 1e12, "frac": ops_s / peak_ops}
+            continue
+        ops = (66.0 + 41.0) / 2
         v["roofline"] = {"bound": "alu", "ops_per_pair": ops, "achieved_Tops": v["pair_evals_per_s"] * ops / 1e12,
                          "peak_Tops": peak_ops / 1e12, "frac": v["pair_evals_per_s"] * ops / peak_ops}
     forms["jastrow_f32"] = jforms

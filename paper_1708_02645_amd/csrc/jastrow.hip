@@ -313,6 +313,135 @@ __global__ __launch_bounds__(kJEvalMaxThreads) void jastrow_eval_kernel(EvalJArg
     }
 }
 
+// Symmetric evaluation for n_elec <= kSymMaxElec: every unordered
+// electron pair is formed once and its terms go to both electrons (the
+// gradient with opposite signs).  The electrons are cut into nb blocks of 64,
+// one wave each (lane l owns electron 64 I + l of block I).  Wave I visits
+// the partner blocks J = I + delta (mod nb), delta = 0 .. nb/2; in block J
+// its lane l meets electron 64 J + ((l + s) mod 64) at step s, so at every
+// step the lanes meet 64 different partners: each lane adds the pair to its
+// own row sums in registers and the partner's share to that partner's
+// column sums in LDS (no two lanes touch one column in a step).  The
+// diagonal block takes steps 1..32 (step 32 on lanes 0..31 only), and when
+// nb is even the block half-way round is split between its two waves (steps
+// 0..31 from one side, 1..32 from the other, which are the pairs of steps
+// 32..63 seen from the first).  Each wave then adds, in the order delta =
+// 0 .. nb/2, the column sums destined for its block to its row sums: the
+// result is deterministic.
+constexpr int kSymMaxElec = 512;
+constexpr int kSymMaxBlocks = kSymMaxElec / 64;
+
+__device__ inline JFun jsel(bool c, const JFun& a, const JFun& b)
+{
+    JFun f;
+    f.rcut = c ? a.rcut : b.rcut;
+    f.hinv = c ? a.hinv : b.hinv;
+    f.m = c ? a.m : b.m;
+    f.off = c ? a.off : b.off;
+    return f;
+}
+
+__global__ __launch_bounds__(kSymMaxElec) void jastrow_eval_sym_kernel(EvalJArgs a)
+{
+    extern __shared__ unsigned char lds[];
+    JStage st;
+    const int N = a.j.n_elec, nb = (N + 63) / 64, D = nb / 2;
+    j_stage(a.j, lds, st);
+    float4* p = reinterpret_cast<float4*>(lds + ((reinterpret_cast<uintptr_t>(st.isp + a.j.n_ion) -
+                                                  reinterpret_cast<uintptr_t>(lds) + 15) & ~uintptr_t(15)));
+    float4* col = p + 64 * nb;  // column sums [wave][delta 0..D][64]
+    __shared__ float red[kSymMaxBlocks];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t w = blockIdx.x;
+    const float* Rx = a.R + w * a.wstride;
+    for (int i = tid; i < 64 * nb; i += blockDim.x)
+        p[i] = i < N ? make_float4(Rx[i], Rx[a.ld + i], Rx[2 * a.ld + i], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < 64 * nb * (D + 1); i += blockDim.x) col[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    const float L0 = a.j.L[0], L1 = a.j.L[1], L2 = a.j.L[2];
+    const float I0 = a.j.Linv[0], I1 = a.j.Linv[1], I2 = a.j.Linv[2];
+    const int nup = a.j.n_up;
+    const JFun fsame = st.fun[a.j.ns], fdiff = st.fun[a.j.ns + 1];
+    const int e = 64 * wv + lane;  // this lane's electron
+    const bool e_ok = e < N, e_up = e < nup;
+    const float4 pe = p[e];
+    float v = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, lap = 0.f;
+    for (int delta = 0; delta <= D; ++delta) {
+        const int J = (wv + delta) % nb;
+        int s0 = 0, s1 = 64;  // steps [s0, s1)
+        if (delta == 0) {
+            s0 = 1;
+            s1 = 33;
+        } else if (2 * delta == nb) {
+            if (wv < D) s1 = 32;
+            else {
+                s0 = 1;
+                s1 = 33;
+            }
+        }
+        float4* cs = col + (wv * (D + 1) + delta) * 64;
+        for (int s = s0; s < s1; ++s) {
+            const int c = (lane + s) & 63, b = 64 * J + c;
+            // the last diagonal step pairs lane l with l + 32 and l + 32 with l: keep one
+            const bool ok = e_ok && b < N && !(delta == 0 && s == 32 && lane >= 32);
+            const float4 pb = p[b];
+            const JFun f = jsel(e_up == (b < nup), fsame, fdiff);
+            const float dx = min_image(pe.x - pb.x, L0, I0), dy = min_image(pe.y - pb.y, L1, I1),
+                        dz = min_image(pe.z - pb.z, L2, I2);
+            float rinv;
+            const float d = pair_dist(dx, dy, dz, rinv);
+            float u, du, d2u;
+            functor(f, st.coefs, d, u, du, d2u);
+            const float q = ok ? du * rinv : 0.f;
+            const float lt = ok ? (rinv > 0.f ? d2u : 0.f) + 2.f * q : 0.f;  // as pair_terms at distance 0
+            v += ok ? u : 0.f;
+            gx = fmaf(q, dx, gx);
+            gy = fmaf(q, dy, gy);
+            gz = fmaf(q, dz, gz);
+            lap += lt;
+            float4 cc = cs[c];
+            cc.x = fmaf(-q, dx, cc.x);
+            cc.y = fmaf(-q, dy, cc.y);
+            cc.z = fmaf(-q, dz, cc.z);
+            cc.w += lt;
+            cs[c] = cc;
+            // Another lane reads this column at the next step: keep the
+            // compiler from moving LDS accesses across steps (the LDS runs a
+            // wave's accesses in order).
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    // column sums destined for this wave's block, in the order delta = 0 .. D
+    for (int delta = 0; delta <= D; ++delta) {
+        const int I = (wv - delta + nb) % nb;
+        const float4 cc = col[(I * (D + 1) + delta) * 64 + lane];
+        gx += cc.x;
+        gy += cc.y;
+        gz += cc.z;
+        lap += cc.w;
+    }
+    float v1 = 0.f;
+    if (e_ok) {
+        for (int I = 0; I < a.j.n_ion; ++I)
+            pair_terms(st.fun[st.isp[I]], st.coefs, min_image(pe.x - st.ix[I], L0, I0),
+                       min_image(pe.y - st.iy[I], L1, I1), min_image(pe.z - st.iz[I], L2, I2), v1, gx, gy, gz, lap);
+        float* Gw = a.G + w * 3 * (int64_t)N;
+        Gw[e] = gx;
+        Gw[N + e] = gy;
+        Gw[2 * N + e] = gz;
+        a.L[w * (int64_t)N + e] = lap;
+    }
+    float jpart = wave_sum(v + v1);
+    if (lane == 0) red[wv] = jpart;
+    __syncthreads();
+    if (tid == 0) {
+        float t = red[0];
+        for (int q = 1; q < nb; ++q) t += red[q];
+        a.J[w] = t;
+    }
+}
+
 struct RowArgs {
     JArgs j;
     const float* R;
@@ -565,6 +694,15 @@ int jastrow_evaluate(const jastrow_t* j, const float* R_dev, int64_t ld, int64_t
     void* params[] = {&a};
     const size_t lds = stage_bytes(j) + 16 + 16 * (size_t)j->d.n_elec;
     const int threads = std::min(kJEvalMaxThreads, std::max(64, (j->d.n_elec + 63) / 64 * 64));
+    const int nb = (j->d.n_elec + 63) / 64;
+    // symmetric pairs: positions padded to whole blocks, then the column sums
+    const size_t slds = stage_bytes(j) + 16 + 16 * 64 * (size_t)nb * (1 + (nb / 2 + 1));
+    if (j->d.n_elec <= kSymMaxElec && slds <= 64 * 1024) {
+        QS_HIP(hipLaunchKernel((const void*)&jastrow_eval_sym_kernel, dim3((unsigned)W), dim3(64 * nb), params, slds,
+                               static_cast<hipStream_t>(stream)));
+        QS_HIP(hipGetLastError());
+        return SPL_OK;
+    }
     QS_HIP(hipLaunchKernel((const void*)&jastrow_eval_kernel, dim3((unsigned)W), dim3(threads), params, lds,
                            static_cast<hipStream_t>(stream)));
     QS_HIP(hipGetLastError());

@@ -117,8 +117,11 @@ def test_full_workload_moves_sampled(torch, q):
     _check_moves(S, R, ks[idx], rnew[idx], idx, out[idx], "full moves")
 
 
-@pytest.mark.parametrize("n_elec,n_up", [(12, 5), (64, 32), (97, 40)])
+@pytest.mark.parametrize("n_elec,n_up", [(12, 5), (64, 32), (97, 40), (200, 70), (600, 300)])
 def test_evaluate_against_oracle(torch, q, n_elec, n_up):
+    """Up to 512 electrons every unordered pair is formed once (blocks of
+    64, ragged last block, the spin boundary inside a block); above that,
+    each electron's row of pairs (600)."""
     J, S, d = _make(q, n_elec=n_elec, n_up=n_up)
     Wn = 3
     R = W.make_electrons(Wn, n_elec)
