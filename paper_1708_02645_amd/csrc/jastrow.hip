@@ -19,9 +19,11 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/qmcjastrow.h"
+
 #include "common.hpp"
 
 namespace qs {
@@ -320,8 +322,9 @@ __global__ __launch_bounds__(kJEvalMaxThreads) void jastrow_eval_kernel(EvalJArg
 // the partner blocks J = I + delta (mod nb), delta = 0 .. nb/2; in block J
 // its lane l meets electron 64 J + ((l + s) mod 64) at step s, so at every
 // step the lanes meet 64 different partners: each lane adds the pair to its
-// own row sums in registers and the partner's share to that partner's
-// column sums in LDS (no two lanes touch one column in a step).  The
+// own row sums and the partner's share to the column sums it holds for that
+// partner, which then move down one lane; at the end of the block they go
+// to LDS.  The
 // diagonal block takes steps 1..32 (step 32 on lanes 0..31 only), and when
 // nb is even the block half-way round is split between its two waves (steps
 // 0..31 from one side, 1..32 from the other, which are the pairs of steps
@@ -356,7 +359,6 @@ __global__ __launch_bounds__(kSymMaxElec) void jastrow_eval_sym_kernel(EvalJArgs
     const float* Rx = a.R + w * a.wstride;
     for (int i = tid; i < 64 * nb; i += blockDim.x)
         p[i] = i < N ? make_float4(Rx[i], Rx[a.ld + i], Rx[2 * a.ld + i], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i = tid; i < 64 * nb * (D + 1); i += blockDim.x) col[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     const float L0 = a.j.L[0], L1 = a.j.L[1], L2 = a.j.L[2];
     const float I0 = a.j.Linv[0], I1 = a.j.Linv[1], I2 = a.j.Linv[2];
@@ -379,37 +381,58 @@ __global__ __launch_bounds__(kSymMaxElec) void jastrow_eval_sym_kernel(EvalJArgs
                 s1 = 33;
             }
         }
-        float4* cs = col + (wv * (D + 1) + delta) * 64;
-        for (int s = s0; s < s1; ++s) {
+        // Column sums in registers: at step s lane l holds those of partner
+        // (l + s) mod 64; after each step they move down one lane, so lane l
+        // then holds those of (l + s + 1) mod 64.
+        float cx = 0.f, cy = 0.f, cz = 0.f, cw = 0.f;
+        // One step.  MASK: some pair of the step may not exist (padding
+        // electrons, the half last diagonal step); SEL: the partner block
+        // holds both spins, so the functor is chosen per pair.
+        auto step = [&](int s, auto mask_t, auto sel_t, const JFun& fblk) {
+            constexpr bool MASK = decltype(mask_t)::value, SEL = decltype(sel_t)::value;
             const int c = (lane + s) & 63, b = 64 * J + c;
-            // the last diagonal step pairs lane l with l + 32 and l + 32 with l: keep one
-            const bool ok = e_ok && b < N && !(delta == 0 && s == 32 && lane >= 32);
             const float4 pb = p[b];
-            const JFun f = jsel(e_up == (b < nup), fsame, fdiff);
+            const JFun f = SEL ? jsel(e_up == (b < nup), fsame, fdiff) : fblk;
             const float dx = min_image(pe.x - pb.x, L0, I0), dy = min_image(pe.y - pb.y, L1, I1),
                         dz = min_image(pe.z - pb.z, L2, I2);
             float rinv;
             const float d = pair_dist(dx, dy, dz, rinv);
             float u, du, d2u;
             functor(f, st.coefs, d, u, du, d2u);
-            const float q = ok ? du * rinv : 0.f;
-            const float lt = ok ? (rinv > 0.f ? d2u : 0.f) + 2.f * q : 0.f;  // as pair_terms at distance 0
-            v += ok ? u : 0.f;
+            float q = du * rinv;
+            float lt = (rinv > 0.f ? d2u : 0.f) + 2.f * q;  // as pair_terms at distance 0
+            if constexpr (MASK) {
+                // the last diagonal step pairs lane l with l + 32 and l + 32 with l: keep one
+                const bool ok = e_ok && b < N && !(delta == 0 && s == 32 && lane >= 32);
+                q = ok ? q : 0.f;
+                lt = ok ? lt : 0.f;
+                u = ok ? u : 0.f;
+            }
+            v += u;
             gx = fmaf(q, dx, gx);
             gy = fmaf(q, dy, gy);
             gz = fmaf(q, dz, gz);
             lap += lt;
-            float4 cc = cs[c];
-            cc.x = fmaf(-q, dx, cc.x);
-            cc.y = fmaf(-q, dy, cc.y);
-            cc.z = fmaf(-q, dz, cc.z);
-            cc.w += lt;
-            cs[c] = cc;
-            // Another lane reads this column at the next step: keep the
-            // compiler from moving LDS accesses across steps (the LDS runs a
-            // wave's accesses in order).
-            __builtin_amdgcn_wave_barrier();
+            cx = __shfl(fmaf(-q, dx, cx), lane + 1, 64);
+            cy = __shfl(fmaf(-q, dy, cy), lane + 1, 64);
+            cz = __shfl(fmaf(-q, dz, cz), lane + 1, 64);
+            cw = __shfl(cw + lt, lane + 1, 64);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        // wave-uniform: every electron of this wave and of block J exists, and
+        // block J holds one spin only
+        const bool full = 64 * wv + 64 <= N && 64 * J + 64 <= N;
+        const bool mixed = 64 * J < nup && nup < 64 * J + 64;
+        const JFun fblk = jsel(e_up == (64 * J < nup), fsame, fdiff);
+        const int s_end = delta == 0 ? s1 - 1 : s1;  // the half last diagonal step is masked
+        if (full && !mixed) {
+            for (int s = s0; s < s_end; ++s) step(s, F(), F(), fblk);
+        } else {
+            for (int s = s0; s < s_end; ++s) step(s, T(), T(), fblk);
         }
+        if (s_end < s1) step(s_end, T(), T(), fblk);
+        col[(wv * (D + 1) + delta) * 64 + ((lane + s1) & 63)] = make_float4(cx, cy, cz, cw);
     }
     __syncthreads();
     // column sums destined for this wave's block, in the order delta = 0 .. D
