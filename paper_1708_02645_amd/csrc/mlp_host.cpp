@@ -140,6 +140,11 @@ struct spline_mlp_s {
     int64_t step;
     int nbins;
     int64_t meta_host[4];  // step, nbins: staged for asynchronous copies
+    // Host copy of the error map (nbins^3 bin errors) as of the last
+    // creation, attach or spline_mlp_build_error_map: lets an evaluation
+    // whose tolerance routes every bin (or none) skip the network (or the
+    // routing).
+    std::vector<float> bin_err_host;
 };
 
 namespace qs {
@@ -167,6 +172,16 @@ static int launch_forward(const spline_mlp_s* m, const double* pos, int64_t B, f
 {
     if (B == 0) return SPL_OK;
     return launch_mlp_forward(fwd_args(m, pos, B, V, G, L), st);
+}
+
+// Refreshes the host copy of the error map from the device (synchronous).
+static int read_map(spline_mlp_s* m, hipStream_t st)
+{
+    m->bin_err_host.assign((size_t)m->nbins * m->nbins * m->nbins, 0.f);
+    QS_HIP(hipMemcpyAsync(m->bin_err_host.data(), m->dev + m->lay.bin_err, m->bin_err_host.size() * sizeof(float),
+                          hipMemcpyDeviceToHost, st));
+    QS_HIP(hipStreamSynchronize(st));
+    return SPL_OK;
 }
 
 static int write_meta(spline_mlp_s* m, hipStream_t st)
@@ -367,6 +382,7 @@ int spline_mlp_create(const spline_mlp_desc* desc, const int32_t* freqs_host, co
         return fail(SPL_EHIP, "initialisation kernels failed to launch");
     }
     m->nbins = 1;
+    m->bin_err_host.assign(1, INFINITY);
     rc = write_meta(m, st);
     if (rc) {
         delete m;
@@ -396,6 +412,11 @@ int spline_mlp_attach(const spline_mlp_desc* desc, const double* cell, void* par
     if (m->step < 0 || m->nbins < 1 || m->nbins > kMaxBins) {
         delete m;
         return fail(SPL_EINVAL, "parameter buffer does not hold a network state");
+    }
+    rc = read_map(m, st);
+    if (rc) {
+        delete m;
+        return rc;
     }
     *out = m;
     return SPL_OK;
@@ -560,7 +581,8 @@ int spline_mlp_build_error_map(spline_mlp_t* m, const spline_t* table, const dou
                        reinterpret_cast<float*>(m->dev + m->lay.bin_err), nb3);
     QS_HIP(hipGetLastError());
     m->nbins = bins_per_dim;
-    return write_meta(m, st);
+    rc = write_meta(m, st);
+    return rc ? rc : read_map(m, st);
 }
 
 size_t spline_mlp_eval_workspace_bytes(int64_t B)
@@ -579,8 +601,7 @@ int spline_mlp_eval_vgl(const spline_mlp_t* m, const spline_t* fallback, float t
     int rc = check_dev(m);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    rc = launch_forward(m, pos, B, V, G, L, st);
-    if (rc || !fallback) return rc;
+    if (!fallback) return launch_forward(m, pos, B, V, G, L, st);
     if (fallback->norb != m->nout || fallback->store == SPL_F64)
         return fail(SPL_EINVAL, "fallback table must have N orbitals and FP32 outputs");
     if (fallback->general) return fail(SPL_EUNSUPPORTED, "the fallback table must have an orthorhombic cell");
@@ -590,13 +611,31 @@ int spline_mlp_eval_vgl(const spline_mlp_t* m, const spline_t* fallback, float t
     int32_t* list = static_cast<int32_t*>(ws);
     int32_t* count = n_fallback ? n_fallback
                                 : reinterpret_cast<int32_t*>(static_cast<unsigned char*>(ws) + a256((size_t)B * 4));
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned int*>(count), 0u, 1);
-    hipLaunchKernelGGL(route_kernel, dim3(grid1(B)), dim3(kThreads), 0, st, pos, m->cell[0], m->cell[1], m->cell[2],
-                       m->nbins, reinterpret_cast<const float*>(m->dev + m->lay.bin_err), tol, B, list, count);
-    QS_HIP(hipGetLastError());
     const spline_tile t = fallback->tile;
     const Variant* v = find_variant(fallback->store, t.cw, t.nch, t.lpp, true);
     if (!v) return fail(SPL_EUNSUPPORTED, "fallback tile shape not compiled");
+    // Bins above tol, from the host copy of the map: when it routes every
+    // bin the network is not run (every row is the table's), when it routes
+    // none the routing is skipped (every row is the network's).  The outputs
+    // are those of the general path either way.
+    size_t routed = 0;
+    for (float e : m->bin_err_host) routed += !(e <= tol);
+    if (!m->bin_err_host.empty() && routed == m->bin_err_host.size()) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned int*>(count),
+                           (unsigned int)B, 1);
+        QS_HIP(hipGetLastError());
+        return launch(*v, make_args(fallback, t, pos, B, V, G, L), st);
+    }
+    rc = launch_forward(m, pos, B, V, G, L, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned int*>(count), 0u, 1);
+    if (!m->bin_err_host.empty() && routed == 0) {
+        QS_HIP(hipGetLastError());
+        return SPL_OK;
+    }
+    hipLaunchKernelGGL(route_kernel, dim3(grid1(B)), dim3(kThreads), 0, st, pos, m->cell[0], m->cell[1], m->cell[2],
+                       m->nbins, reinterpret_cast<const float*>(m->dev + m->lay.bin_err), tol, B, list, count);
+    QS_HIP(hipGetLastError());
     EvalArgs a = make_args(fallback, t, pos, B, V, G, L);
     a.idx = list;
     a.nidx = count;

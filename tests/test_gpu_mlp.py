@@ -142,6 +142,12 @@ def test_training_error_map_fallback_and_resume(torch, q, oracle, small_table):
     # no fallback table: network only
     V2, _, _, _ = net.eval_vgl(pos, fallback=None)
     np.testing.assert_array_equal(V2.cpu().numpy(), plain[0].cpu().numpy())
+    # a tolerance above every bin error: nothing is routed -> network exactly
+    V3, G3, L3, nf3 = net.eval_vgl(pos, fallback=spl, tol=float(errs[-1]) * 2 + 1.0)
+    torch.cuda.synchronize()
+    assert int(nf3.cpu()[0]) == 0
+    for a, b in zip((V3, G3, L3), plain):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
 
     # resume from a saved state
     st = net.state()
@@ -149,6 +155,11 @@ def test_training_error_map_fallback_and_resume(torch, q, oracle, small_table):
     assert net2.info() == net.info()
     for a, b in zip(net2.forward(pos), plain):
         np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    # the resumed network routes by the same map
+    V4, _, _, nf4 = net2.eval_vgl(pos, fallback=spl, tol=tol)
+    torch.cuda.synchronize()
+    assert int(nf4.cpu()[0]) == n
+    np.testing.assert_array_equal(V4.cpu().numpy(), V.cpu().numpy())
     net2.train_step(pos[:4096], spl.eval_vgl(pos[:4096]), lr=1e-4)
     assert net2.info()["step"] == 301
 
