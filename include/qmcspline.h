@@ -163,9 +163,14 @@ int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
 int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
                          size_t workspace_bytes, void* stream);
 /* spline_eval_vgh in locality order (same arguments and results, bit for
- * bit; the VGH-family tile shape), with the workspace above. */
+ * bit), with the workspace above.  Its shape: 16-lane groups with the widest
+ * chunk compiled for the storage type where it fits the row (else the
+ * VGH-family tile's), at most 8 positions per workgroup; a general cell's
+ * spline_eval_vgl_sorted uses the same.  spline_get_sorted_vgh_tile reads
+ * it. */
 int spline_eval_vgh_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* H,
                            void* workspace_dev, size_t workspace_bytes, void* stream);
+int spline_get_sorted_vgh_tile(const spline_t* s, spline_tile* tile);
 /* The fused determinant ratio in locality order: arguments and errors of
  * spline_eval_ratio_vgl / spline_eval_ratio_v, plus the workspace of
  * spline_eval_vgl_sorted.  Uses the sorted tile shape (the sorted value

@@ -101,6 +101,7 @@ def lib():
             "spline_get_tile": ([p, p], ctypes.c_int),
             "spline_get_value_tile": ([p, p], ctypes.c_int),
             "spline_get_sorted_value_tile": ([p, p], ctypes.c_int),
+            "spline_get_sorted_vgh_tile": ([p, p], ctypes.c_int),
             "spline_autotune": ([p, p, i64, p, p, p, i32, ctypes.c_char_p, p, p], ctypes.c_int),
             "spline_get_info": ([p, p, p, p, p], ctypes.c_int),
             "spline_destroy": ([p], ctypes.c_int),
@@ -377,6 +378,11 @@ class Spline:
     def get_sorted_value_tile(self):
         t = Tile()
         check(lib().spline_get_sorted_value_tile(self._h, ctypes.byref(t)))
+        return t.astuple()
+
+    def get_sorted_vgh_tile(self):
+        t = Tile()
+        check(lib().spline_get_sorted_vgh_tile(self._h, ctypes.byref(t)))
         return t.astuple()
 
     def autotune_sorted(self, pos, reps: int = 5, cache_path: str | None = None, out=None, workspace=None,

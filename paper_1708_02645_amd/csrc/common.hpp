@@ -124,9 +124,12 @@ EvalArgs make_args(const spline_s* s, const spline_tile& t, const double* pos, i
 spline_tile default_vgh_tile(const spline_s* s);
 void set_general_args(const spline_s* s, EvalArgs& a);
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
-// (pb > 0: positions per workgroup instead of the VGH tile's.)
-int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
-                       const int32_t* idx, hipStream_t st, int pb = 0);
+int vgh_launch_indexed(const spline_s* s, const spline_tile& t, bool hessian, const double* pos, int64_t B, void* V,
+                       void* G, void* H, const int32_t* idx, hipStream_t st);
+// Tile of the locality-ordered VGH family: 16-lane groups with the widest
+// chunk compiled for the storage type where it fits the row (else the VGH
+// tile's shape), at most 8 positions per workgroup.
+spline_tile vgh_sorted_tile(const spline_s* s);
 // Locality ordering (locality.hip): workspace bytes for B positions, and the
 // device sort of B positions into an index list for workgroups of pb
 // positions (pb <= 0: plain sorted order).

@@ -222,14 +222,11 @@ static int sorted_run(const spline_s* s, const spline_tile& t, bool vgl, const d
 static int sorted_vgh(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
                       void* ws, hipStream_t st)
 {
-    // At most 8 positions per workgroup: fewer positions in flight per XCD
-    // keep more of their shared rows in its L2 (the VGH tile is tuned on the
-    // plain path, where this does not matter).
-    const int pb = std::min(s->htile.pb, 8);
+    const spline_tile t = vgh_sorted_tile(s);
     const int32_t* perm = nullptr;
-    int rc = sort_positions(s, pos, B, pb, ws, st, &perm);
+    int rc = sort_positions(s, pos, B, t.pb, ws, st, &perm);
     if (rc) return rc;
-    return vgh_launch_indexed(s, hessian, pos, B, V, G, H, perm, st, pb);
+    return vgh_launch_indexed(s, t, hessian, pos, B, V, G, H, perm, st);
 }
 
 static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, void* ws,
@@ -397,6 +394,13 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
         if (f && !have_v) f << key << "|" << tv.cw << " " << tv.nch << " " << tv.lpp << " " << tv.pb << "\n";
         if (f && !have_n) f << vkey << "|" << tn.cw << " " << tn.nch << " " << tn.lpp << " " << tn.pb << "\n";
     }
+    return SPL_OK;
+}
+
+int spline_get_sorted_vgh_tile(const spline_t* s, spline_tile* tile)
+{
+    if (!s || !tile) return fail(SPL_EINVAL, "NULL argument");
+    *tile = vgh_sorted_tile(s);
     return SPL_OK;
 }
 

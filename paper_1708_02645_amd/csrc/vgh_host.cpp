@@ -1,6 +1,7 @@
 // Host side of the value-gradient-Hessian family and of general (triclinic)
 // cells: lattice set-up, the grid-to-Cartesian maps passed to the kernels,
 // tile selection and autotuning, and the launches.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -181,13 +182,30 @@ int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* 
 }
 
 // The VGH family (Hessian, or the general-cell Laplacian) through an index
-// list, with the handle's VGH-family tile (locality-ordered evaluation).
-int vgh_launch_indexed(const spline_s* s, bool hessian, const double* pos, int64_t B, void* V, void* G, void* H,
-                       const int32_t* idx, hipStream_t st, int pb)
+// list (locality-ordered evaluation).
+int vgh_launch_indexed(const spline_s* s, const spline_tile& t, bool hessian, const double* pos, int64_t B, void* V,
+                       void* G, void* H, const int32_t* idx, hipStream_t st)
+{
+    return vgh_launch(s, t, hessian ? VGH_OUT_H : VGH_OUT_L, pos, B, V, G, H, st, idx);
+}
+
+// In locality order the rows of neighbouring positions come from cache and
+// the shape decides the speed (on the plain path, bound by HBM, the VGH
+// tuner's candidates are equal within noise, and its pick can be 20% slower
+// here): 16-lane groups with 16-byte (else 8-byte) chunks where they fit.
+spline_tile vgh_sorted_tile(const spline_s* s)
 {
     spline_tile t = s->htile;
-    if (pb > 0) t.pb = pb;
-    return vgh_launch(s, t, hessian ? VGH_OUT_H : VGH_OUT_L, pos, B, V, G, H, st, idx);
+    for (int cw : {4, 2}) {
+        const spline_tile c{cw, 1, 16, t.pb};
+        const VghVariant* v = find_vgh(s->store, c, VGH_OUT_H);
+        if (v && vgh_fits(s, *v) && find_vgh(s->store, c, VGH_OUT_L)) {
+            t = c;
+            break;
+        }
+    }
+    t.pb = std::min(t.pb, 8);  // fewer positions in flight per XCD keep more shared rows in its L2
+    return t;
 }
 
 static int check_outputs(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* H)

@@ -130,6 +130,8 @@ def test_vgh_and_general_cells_equal(torch, q, oracle, dtype):
             ref = s.eval_vgh(pos)
             got = s.eval_vgh_sorted(pos)
             _same(torch, got, ref)
+            st = s.get_sorted_vgh_tile()
+            assert st[2] in (16, s.get_vgh_tile()[2]) and 1 <= st[3] <= 8, st
             if general:
                 _same(torch, s.eval_vgl_sorted(pos), s.eval_vgl(pos))
     deq = coefs if dtype == "f64" else oracle.dequantize(coefs, dtype)[0]
