@@ -144,7 +144,7 @@ def test_vgh_and_general_cells_equal(torch, q, oracle, dtype):
 
 def test_tiles_and_chunk_dealing(torch, q):
     """The index list deals whole chunks of pb sorted slots to the XCDs;
-    every tile (pb 16, 32, 64) and batch size (no whole chunk, a partial last
+    every tile (pb 8, 16, 32, 64) and batch size (no whole chunk, a partial last
     chunk, chunk counts that do and do not divide by 8) must still cover each
     position exactly once."""
     rng = np.random.default_rng(11)
@@ -154,6 +154,8 @@ def test_tiles_and_chunk_dealing(torch, q):
     for t in s.tile_candidates():
         seen.setdefault(t[3], t)
     assert len(seen) >= 2
+    t16 = seen[16]
+    seen[8] = (t16[0], t16[1], t16[2], 8)  # the sorted autotuner's extra chunk length
     for pb, t in sorted(seen.items()):
         s.set_sorted_tile(t)
         assert tuple(s.get_sorted_tile()) == tuple(t)
@@ -162,7 +164,7 @@ def test_tiles_and_chunk_dealing(torch, q):
             _check_equal(torch, s, rng.random((B, 3)))
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_full_size_equal(torch, q, dtype):
     """80^3 grid, 384 orbitals, 196,608 positions (the bench's batch)."""
     grid, N, coefs, _ = W.make_table(3)
