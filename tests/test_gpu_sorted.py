@@ -204,6 +204,10 @@ def test_ratio_small_equal(torch, q, dtype):
         _say("case sorted ratio", dtype, r is None)
         _same(torch, (s.eval_ratio_vgl_sorted(pos, ainv, rows=r),), (s.eval_ratio_vgl(pos, ainv, rows=r),))
         _same(torch, (s.eval_ratio_v_sorted(pos, ainv, rows=r),), (s.eval_ratio_v(pos, ainv, rows=r),))
+    # 8 positions per workgroup (the sums do not depend on it, only on the shape)
+    s.set_sorted_tile((t[0], t[1], t[2], 8))
+    _same(torch, (s.eval_ratio_vgl_sorted(pos, ainv, rows=rows),), (s.eval_ratio_vgl(pos, ainv, rows=rows),))
+    _same(torch, (s.eval_ratio_v_sorted(pos, ainv),), (s.eval_ratio_v(pos, ainv),))
 
 
 def test_ratio_full_size_equal(torch, q):
