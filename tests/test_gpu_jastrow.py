@@ -141,7 +141,11 @@ def test_full_workload_evaluate_sampled(torch, q):
     J, S, d = _make(q)
     Wn, N = 64, d["n_elec"]
     R = W.make_electrons(Wn, N)
-    Jg, Gg, Lg = (t.cpu().numpy().astype(np.float64) for t in J.evaluate(J.positions(R)))
+    Rd = J.positions(R)
+    first = J.evaluate(Rd)
+    again = J.evaluate(Rd)  # fixed order of every sum: the same bits
+    assert all(bool(torch.equal(a, b)) for a, b in zip(first, again))
+    Jg, Gg, Lg = (t.cpu().numpy().astype(np.float64) for t in first)
     for w in (0, Wn - 1):
         Jr, Gr, Lr = S.evaluate(_f32(R[w]))
         sc = np.array([_abs_terms(S, _f32(R[w]), i, _f32(R[w][i])) for i in range(N)])
