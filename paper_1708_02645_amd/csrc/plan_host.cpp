@@ -277,6 +277,7 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     if (tune_reps > 0 && max_tasks > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
             delete p;
             return fail(SPL_EHIP, "hipEventCreate failed");
         }

@@ -617,9 +617,11 @@ int tune_kind(const spline_s* s, bool vgl, const std::vector<spline_tile>& cands
     const size_t nv = (size_t)Bc * s->norb * ob;
     const size_t nq = vgl ? 5 : 1;
     std::vector<unsigned char> ref, cur(nv * nq);
-    hipEvent_t e0, e1;
-    QS_HIP(hipEventCreate(&e0));
-    QS_HIP(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(SPL_EHIP, "hipEventCreate failed");
+    }
     int rc = SPL_OK;
     float best = 1e30f;
     *best_t = cands[0];

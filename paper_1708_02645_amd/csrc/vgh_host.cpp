@@ -232,9 +232,11 @@ int vgh_autotune(spline_s* s, int out, const double* pos, int64_t B, void* V, vo
     const size_t nv = (size_t)Bc * s->norb * ob;
     const size_t nh = out == VGH_OUT_H ? 6 : 1;
     std::vector<unsigned char> ref, cur(nv * (4 + nh));
-    hipEvent_t e0, e1;
-    QS_HIP(hipEventCreate(&e0));
-    QS_HIP(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(SPL_EHIP, "hipEventCreate failed");
+    }
     int rc = SPL_OK;
     float best = 1e30f;
     spline_tile best_t = cands[0];
