@@ -449,6 +449,22 @@ typedef struct {
     int32_t width[4];
 } spline_mlp_desc;
 
+/* Feature frequencies for a table (setup, host only): the `count` integer
+ * vectors k, one of each pair +-k with 0 < |k|_2 <= kmax, whose pair carries
+ * the most energy sum_m |c_hat_m(k)|^2 + |c_hat_m(-k)|^2 in the discrete
+ * Fourier transform c_hat_m(k) = sum_j c_m[j] exp(-2 pi i sum_d k_d j_d /
+ * n_d) of the coefficients coefs_host [n0][n1][n2][n_orb] (host, FP64,
+ * orbital fastest).  The representative of a pair is the lexicographically
+ * larger of k and -k; pairs are ordered by energy, equal energies by
+ * increasing k.  freqs_out: host [count][3] int32.  energy_out (host, may be
+ * NULL): count + 2 doubles -- the chosen pairs' energies, then the energy at
+ * k = 0, then the whole spectrum's (n0 n1 n2 sum c^2, by Parseval), so the
+ * share of the table's energy that the chosen features leave out can be
+ * read.  kmax in [1, 16]; count at most the number of pairs (128 for
+ * kmax = 4).  Uses up to 16 host threads. */
+int spline_mlp_select_frequencies(const spline_grid* grid, int32_t n_orb, const double* coefs_host, int32_t count,
+                                  int32_t kmax, int32_t* freqs_out, double* energy_out);
+
 /* Byte offsets inside the parameter buffer (all 256-byte aligned), and the
  * element offsets of each tensor inside the flat FP32 parameter vector
  * [W1 (256x96) | b1 | W2 (256x256) | b2 | W3 (Nx256) | b3], weights stored
@@ -476,9 +492,12 @@ int spline_mlp_create(const spline_mlp_desc* desc, const int32_t* freqs_host, co
 int spline_mlp_attach(const spline_mlp_desc* desc, const double* cell, void* params_dev, size_t bytes, void* stream,
                       spline_mlp_t** out);
 
-/* Sets mu, sd (per-orbital mean and standard deviation of V) and the loss
- * weights (inverse variances of the normalised V, G, L) from a target batch
- * V [B][N], G [B][3][N], L [B][N] on the device. */
+/* Sets the output map and the loss weights from a target batch V [B][N],
+ * G [B][3][N], L [B][N] (device, B >= 2): mu_n and sd_n are the mean and the
+ * population standard deviation of orbital n's V over the batch (sd floored
+ * at 1e-12); the weight of V, G (components pooled) and L is 1 / the mean
+ * over orbitals of the variance of Q_n / sd_n about its own mean (1 for V).
+ * Statistics are summed in FP64.  Synchronises `stream`. */
 int spline_mlp_init_output(spline_mlp_t* mlp, const float* V, const float* G, const float* L, int64_t B,
                            void* stream);
 
@@ -502,18 +521,26 @@ int spline_mlp_forward(const spline_mlp_t* mlp, const double* pos, int64_t B, fl
 /* Error map: evaluates the network and the spline table it stands in for (same N, same cell, FP32
  * outputs) at n_val validation positions and stores, per spatial bin
  * (bins_per_dim^3 bins, <= 16 per axis), the largest error over its points,
- * orbitals and quantities, each relative to that orbital's largest |V|,
- * |G_d| or |L| over all validation points.  Bins without points are
- * untrusted.  The estimate is empirical, not a bound. */
+ * orbitals and quantities (V, each component of G, L), each relative to
+ * that orbital's largest |V|, |G_d| or |L| of the spline over all
+ * validation points (1 where that is 0).  Bin of a position: along axis d,
+ * floor(nb * f) for its fractional coordinate f = u - floor(u), u = r_d /
+ * cell_d in FP64 (f rounded up to 1 is the last bin; a non-finite
+ * coordinate is bin 0); index (i0 * nb + i1) * nb + i2.  A NaN error term
+ * counts as +inf; bins without points get +inf (untrusted).  The map is FP32
+ * at layout.bin_err.  The estimate is empirical, not a bound. */
 size_t spline_mlp_errmap_workspace_bytes(const spline_mlp_t* mlp, int64_t n_val);
 int spline_mlp_build_error_map(spline_mlp_t* mlp, const spline_t* table, const double* val_pos, int64_t n_val,
                                int32_t bins_per_dim, void* ws, size_t ws_bytes, void* stream);
 
 /* Evaluation with fallback: the network at every position, then the
  * fallback table (may be NULL: network only) re-evaluates, in place, every
- * position whose bin error exceeds tol (tol < 0 routes everything).
- * n_fallback (device int32, may be NULL) receives the number routed.
- * ws: device workspace of spline_mlp_eval_workspace_bytes(B) bytes. */
+ * position whose bin error is not <= tol (compared in FP32: tol < 0 or NaN
+ * routes everything, +inf bins always route unless tol is +inf).  Routed
+ * rows equal spline_eval_vgl's bit for bit, the others
+ * spline_mlp_forward's.  n_fallback (device int32, may be NULL) receives the
+ * number routed.  ws: device workspace of spline_mlp_eval_workspace_bytes(B)
+ * bytes. */
 size_t spline_mlp_eval_workspace_bytes(int64_t B);
 int spline_mlp_eval_vgl(const spline_mlp_t* mlp, const spline_t* fallback, float tol, const double* pos, int64_t B,
                         float* V, float* G, float* L, void* ws, size_t ws_bytes, int32_t* n_fallback, void* stream);

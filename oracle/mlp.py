@@ -1,5 +1,8 @@
 """FP64 oracle of the surrogate network (test infrastructure only).
 
+Only tests/, the smoke check and the benchmark's CPU-baseline leg use this
+module; it shares no code with the GPU library.
+
 A small periodic network stands in for a spline table: positions go through
 periodic Fourier features, then dense layers with SiLU, and the value,
 gradient and Laplacian of the output are carried exactly in forward mode.
@@ -17,10 +20,22 @@ written out plainly in numpy so that each step can be checked by eye.
 The reverse pass (gradients of the Sobolev loss with respect to every weight)
 is hand-written; tests pin it against finite differences of the loss.
 
+BF16 arithmetic model (bf16=True): every operand of every matrix product --
+features, activations, weights, and in the reverse pass the adjoints -- is
+rounded to BF16 (nearest even, from FP32); biases, SiLU streams, the loss and
+the bias gradients stay unrounded.
+
+The spline fallback: the cell is cut into bins_per_dim^3 bins; a bin's error
+is the largest error of the network against the spline over the validation
+points that fall in it, over orbitals and over V, the three components of G
+and L, each error taken relative to that orbital's largest |quantity| over the
+whole validation set; positions in bins whose error exceeds a tolerance are
+routed to the spline.
+
 Parity status: every function here is pinned by tests/test_oracle_mlp.py
-(closed forms and finite differences).  The network's accuracy as a
-surrogate of a spline table has no reference value: parity unpinned,
-measured and reported.
+(closed forms, finite differences, hand-built cases and scalar loops).  The
+network's accuracy as a surrogate of a spline table has no reference value:
+parity unpinned, measured and reported.
 """
 from __future__ import annotations
 
@@ -105,12 +120,26 @@ def forward(params, pos, cell=(1.0, 1.0, 1.0), bf16=False, cache=False):
     return V, G, L
 
 
-def loss_weights(tV, tG, tL, mu, sd):
-    """1 / variance of each normalised target quantity (V, G, L)."""
-    nv = (tV - mu) / sd
-    ng = tG / sd
-    nl = tL / sd
-    return np.array([1.0 / nv.var(), 1.0 / ng.var(), 1.0 / nl.var()])
+def output_normalisation(tV, tG, tL):
+    """Per-orbital output map and loss weights from a batch of targets.
+
+    mu_n, sd_n: mean and (population) standard deviation of orbital n's value
+    over the batch (sd floored at 1e-12).  Loss weight of quantity Q (V; G
+    with its three components pooled; L): 1 / the variance of Q / sd_n about
+    its own per-orbital mean, averaged over orbitals.  For V that is 1 by
+    construction.  Returns (mu[N], sd[N], w[3])."""
+    tV = np.asarray(tV, dtype=np.float64)
+    tG = np.asarray(tG, dtype=np.float64)
+    tL = np.asarray(tL, dtype=np.float64)
+    N = tV.shape[-1]
+    mu = tV.mean(0)
+    sd = np.maximum(np.sqrt(((tV - mu) ** 2).mean(0)), 1e-12)
+    w = []
+    for Q in (tV, tG, tL):
+        q = Q.reshape(-1, N)
+        var = ((q - q.mean(0)) ** 2).mean(0) / (sd * sd)
+        w.append(1.0 / max(var.mean(), 1e-30))
+    return mu, sd, np.array(w)
 
 
 def loss(params, pos, tV, tG, tL, w, cell=(1.0, 1.0, 1.0), bf16=False):
@@ -134,18 +163,23 @@ def _silu_backward(h, dz):
     return {"v": dh_v, "d": dh_d, "L": dh_L}
 
 
-def _linear_backward(W, a, dh):
+def _linear_backward(W, a, dh, bf16=False):
     """Gradients of W (sum over the five streams), b (value stream) and of the
-    layer input streams."""
-    dW = dh["v"].T @ a["v"] + sum(dh["d"][i].T @ a["d"][i] for i in range(3)) + dh["L"].T @ a["L"]
+    layer input streams.  bf16=True rounds the operands of the two products
+    (adjoints, layer inputs, weights) to BF16; the bias gradient is a plain
+    sum of the unrounded value-stream adjoints."""
+    r = bf16_round if bf16 else (lambda x: x)
+    Wm = r(W)
+    dW = r(dh["v"]).T @ r(a["v"]) + sum(r(dh["d"][i]).T @ r(a["d"][i]) for i in range(3)) + r(dh["L"]).T @ r(a["L"])
     db = dh["v"].sum(0)
-    da = {"v": dh["v"] @ W, "d": np.stack([dh["d"][i] @ W for i in range(3)]), "L": dh["L"] @ W}
+    da = {"v": r(dh["v"]) @ Wm, "d": np.stack([r(dh["d"][i]) @ Wm for i in range(3)]), "L": r(dh["L"]) @ Wm}
     return dW, db, da
 
 
-def loss_and_grads(params, pos, tV, tG, tL, w, cell=(1.0, 1.0, 1.0)):
-    """FP64 loss and its gradients with respect to W1..b3 (reverse mode)."""
-    (V, G, L), c = forward(params, pos, cell, cache=True)
+def loss_and_grads(params, pos, tV, tG, tL, w, cell=(1.0, 1.0, 1.0), bf16=False):
+    """Loss and its gradients with respect to W1..b3 (reverse mode), in FP64;
+    bf16=True follows the BF16 arithmetic model in both passes."""
+    (V, G, L), c = forward(params, pos, cell, bf16=bf16, cache=True)
     sd = params["sd"]
     B, N = V.shape
     eV = (V - tV) / sd
@@ -157,9 +191,74 @@ def loss_and_grads(params, pos, tV, tG, tL, w, cell=(1.0, 1.0, 1.0)):
           "d": np.transpose(2.0 * w[1] * eG / (3 * B * N), (1, 0, 2)),
           "L": 2.0 * w[2] * eL / (B * N)}
     g = {}
-    g["W3"], g["b3"], dz2 = _linear_backward(params["W3"], c["z2"], dy)
+    g["W3"], g["b3"], dz2 = _linear_backward(params["W3"], c["z2"], dy, bf16)
     dh2 = _silu_backward(c["h2"], dz2)
-    g["W2"], g["b2"], dz1 = _linear_backward(params["W2"], c["z1"], dh2)
+    g["W2"], g["b2"], dz1 = _linear_backward(params["W2"], c["z1"], dh2, bf16)
     dh1 = _silu_backward(c["h1"], dz1)
-    g["W1"], g["b1"], _ = _linear_backward(params["W1"], c["a0"], dh1)
+    g["W1"], g["b1"], _ = _linear_backward(params["W1"], c["a0"], dh1, bf16)
     return lval, g
+
+
+def bin_index(pos, bins_per_dim, cell=(1.0, 1.0, 1.0)):
+    """Error-map bin of each position: (i0 * nb + i1) * nb + i2.
+
+    Along axis d the fractional coordinate f = u - floor(u), u = r_d / cell_d
+    (FP64), falls in bin floor(nb * f).  An f that rounds up to 1 (a
+    coordinate just below a multiple of the cell) belongs to the last bin; a
+    non-finite coordinate is put in bin 0."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    nb = int(bins_per_dim)
+    idx = np.zeros(pos.shape[0], dtype=np.int64)
+    for d in range(3):
+        u = pos[:, d] / float(cell[d])
+        with np.errstate(invalid="ignore"):
+            f = u - np.floor(u)
+            i = np.floor(f * nb)
+        i = np.where(np.isfinite(i), i, 0.0)
+        i = np.clip(i, 0, nb - 1).astype(np.int64)
+        idx = idx * nb + i
+    return idx
+
+
+def point_errors(net_vgl, spline_vgl):
+    """Per-position error of the network against the spline: max over
+    orbitals of |dV| / sV_n, |dG_d| / sG_n (each component), |dL| / sL_n,
+    with sQ_n the largest |Q| of orbital n over all the given positions (1 if
+    that is 0).  A NaN anywhere in a position's terms makes its error +inf."""
+    V, G, L = (np.asarray(x, dtype=np.float64) for x in net_vgl)
+    Vs, Gs, Ls = (np.asarray(x, dtype=np.float64) for x in spline_vgl)
+    B, N = Vs.shape
+    terms = []
+    for Q, Qs in ((V, Vs), (G, Gs), (L, Ls)):
+        with np.errstate(invalid="ignore"):
+            s = np.abs(Qs).reshape(-1, N).max(0) if B else np.ones(N)
+        s = np.where(s == 0, 1.0, s)
+        with np.errstate(invalid="ignore"):
+            terms.append((np.abs(Q - Qs) / s).reshape(B, -1))
+    t = np.concatenate(terms, 1)
+    with np.errstate(invalid="ignore"):
+        e = t.max(1) if t.shape[1] else np.zeros(B)
+    return np.where(np.isnan(t).any(1), np.inf, e)
+
+
+def error_map(net_vgl, spline_vgl, val_pos, bins_per_dim, cell=(1.0, 1.0, 1.0)):
+    """bin_err[nb^3]: per bin the largest point error (point_errors) over the
+    validation positions in it; +inf for a bin that holds none."""
+    nb = int(bins_per_dim)
+    e = point_errors(net_vgl, spline_vgl)
+    k = bin_index(val_pos, nb, cell)
+    out = np.full(nb ** 3, -np.inf)
+    np.maximum.at(out, k, e)
+    return np.where(np.isneginf(out), np.inf, out)
+
+
+def route(pos, bin_err, bins_per_dim, tol, cell=(1.0, 1.0, 1.0)):
+    """Sorted indices of the positions routed to the spline: those whose bin
+    error is not <= tol (so +inf and NaN bins always route, and a NaN
+    tolerance routes everything).  The comparison is taken in FP32, the
+    precision of a stored map and tolerance."""
+    e = np.asarray(bin_err, dtype=np.float32)[bin_index(pos, bins_per_dim, cell)]
+    t = np.float32(tol)
+    with np.errstate(invalid="ignore"):
+        keep = e <= t
+    return np.flatnonzero(~keep).astype(np.int64)

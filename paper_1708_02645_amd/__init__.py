@@ -679,6 +679,7 @@ _MLP_SIGS = {
     "spline_mlp_eval_vgl": (["p", "p", "f", "p", "i64", "p", "p", "p", "p", "sz", "p", "p"], "i"),
     "spline_mlp_get_info": (["p", "p", "p"], "i"),
     "spline_mlp_destroy": (["p"], "i"),
+    "spline_mlp_select_frequencies": (["p", "i32", "p", "i32", "i32", "p", "p"], "i"),
 }
 
 
@@ -710,33 +711,25 @@ def mlp_layout(norb: int) -> MlpLayout:
     return out
 
 
-def spectral_frequencies(coefs: np.ndarray, count: int = 48, kmax: int = 4) -> np.ndarray:
+def spectral_frequencies(coefs: np.ndarray, count: int = 48, kmax: int = 4, with_energy: bool = False):
     """The `count` integer frequency vectors (one of each +-k pair, 0 < |k| <= kmax)
-    carrying the most energy in the table's coefficients, summed over orbitals.
-
-    Setup of the surrogate's features (not on the evaluation path): the
-    discrete Fourier transform of each orbital's coefficient grid, energy
-    |c_hat(k)|^2 + |c_hat(-k)|^2 per pair."""
-    c = np.asarray(coefs, dtype=np.float64)
-    n = c.shape[:3]
-    r = np.arange(-kmax, kmax + 1)
-    ks = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
-    ks = ks[((ks * ks).sum(1) <= kmax * kmax) & ((ks * ks).sum(1) > 0)]
-    energy = np.zeros(len(ks))
-    for m0 in range(0, c.shape[3], 32):
-        F = np.fft.fftn(c[..., m0:m0 + 32], axes=(0, 1, 2))
-        for i, k in enumerate(ks):
-            energy[i] += (np.abs(F[k[0] % n[0], k[1] % n[1], k[2] % n[2]]) ** 2).sum()
-    # keep one representative of each +-k pair (the lexicographically larger)
-    keep = [i for i, k in enumerate(ks) if tuple(k) > tuple(-k)]
-    pair_e = {tuple(ks[i]): energy[i] for i in keep}
-    for i, k in enumerate(ks):
-        if tuple(k) < tuple(-k):
-            pair_e[tuple(-k)] += energy[i]
-    order = sorted(pair_e, key=lambda k: (-pair_e[k], k))
-    if len(order) < count:
-        raise ValueError("fewer than %d frequency pairs with |k| <= %d" % (count, kmax))
-    return np.array(order[:count], dtype=np.int32)
+    carrying the most energy in the table's coefficients, summed over orbitals
+    (spline_mlp_select_frequencies).  with_energy=True also returns a dict of
+    the chosen pairs' energies, the energy at k = 0 and the whole spectrum's."""
+    c = np.ascontiguousarray(coefs, dtype=np.float64)
+    if c.ndim != 4:
+        raise ValueError("coefs must be [n0, n1, n2, N]")
+    g = Grid()
+    for d in range(3):
+        g.n[d] = c.shape[d]
+        g.cell[d] = 1.0
+    out = np.zeros((int(count), 3), dtype=np.int32)
+    en = np.zeros(int(count) + 2)
+    check(_mlp_lib().spline_mlp_select_frequencies(ctypes.byref(g), c.shape[3], c.ctypes.data, int(count), int(kmax),
+                                                   out.ctypes.data, en.ctypes.data))
+    if with_energy:
+        return out, {"pairs": en[:count].copy(), "k0": float(en[count]), "total": float(en[count + 1])}
+    return out
 
 
 def flatten_mlp_params(Ws, bs) -> np.ndarray:

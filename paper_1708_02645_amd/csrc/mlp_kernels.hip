@@ -240,8 +240,9 @@ __device__ inline int bin_of(const double* pos, int64_t b, const double* cell, i
     for (int d = 0; d < 3; ++d) {
         double f = pos[3 * b + d] / cell[d];
         f -= floor(f);
-        int i = (int)(f * nb);
-        i = i < 0 ? 0 : (i >= nb ? nb - 1 : i);  // NaN -> 0
+        const double x = f * nb;
+        // f rounded up to 1 is the last bin; a non-finite coordinate is bin 0
+        const int i = (x >= 0.0 && x < (double)nb) ? (int)x : (x >= (double)nb ? nb - 1 : 0);
         idx = idx * nb + i;
     }
     return idx;
@@ -259,6 +260,10 @@ __global__ void colmax_kernel(const float* V, const float* G, const float* L, in
     atomicMax(&smax[2 * N + n], __float_as_uint(fabsf(L[i])));
 }
 
+// A point's error: the largest over orbitals of |dV| / sV, |dG_d| / sG and
+// |dL| / sL, each normaliser the orbital's largest |quantity| over the
+// validation set (1 if that is 0).  A NaN term makes the error +inf, whose
+// bits order above every finite error.
 __global__ void bin_error_kernel(const double* pos, double c0, double c1, double c2, int nbins, const float* Vm,
                                  const float* Gm, const float* Lm, const float* Vs, const float* Gs, const float* Ls,
                                  const unsigned int* smax, int64_t B, int N, unsigned int* bin_err)
@@ -268,13 +273,21 @@ __global__ void bin_error_kernel(const double* pos, double c0, double c1, double
     const int64_t b = i / N;
     const int n = (int)(i - b * N);
     const double cell[3] = {c0, c1, c2};
-    const float sv = fmaxf(__uint_as_float(smax[n]), 1e-30f);
-    const float sg = fmaxf(__uint_as_float(smax[N + n]), 1e-30f);
-    const float sl = fmaxf(__uint_as_float(smax[2 * N + n]), 1e-30f);
-    float e = fabsf(Vm[i] - Vs[i]) / sv;
-    for (int d = 0; d < 3; ++d) e = fmaxf(e, fabsf(Gm[(3 * b + d) * N + n] - Gs[(3 * b + d) * N + n]) / sg);
-    e = fmaxf(e, fabsf(Lm[i] - Ls[i]) / sl);
-    if (!(e == e)) e = 3.0e38f;  // NaN counts as the worst error
+    auto norm = [](unsigned int bits) {
+        const float s = __uint_as_float(bits);
+        return s == 0.0f ? 1.0f : s;
+    };
+    const float sv = norm(smax[n]), sg = norm(smax[N + n]), sl = norm(smax[2 * N + n]);
+    float e = 0.0f;
+    bool nan = false;
+    auto take = [&](float x) {
+        nan |= !(x == x);
+        e = fmaxf(e, x);
+    };
+    take(fabsf(Vm[i] - Vs[i]) / sv);
+    for (int d = 0; d < 3; ++d) take(fabsf(Gm[(3 * b + d) * N + n] - Gs[(3 * b + d) * N + n]) / sg);
+    take(fabsf(Lm[i] - Ls[i]) / sl);
+    if (nan) e = __builtin_inff();
     atomicMax(&bin_err[bin_of(pos, b, cell, nbins)], __float_as_uint(e));
 }
 
