@@ -113,7 +113,7 @@ def test_gradient_matches_oracle(torch, q, oracle, small_table):
     the loss and the accumulations, and the rare BF16 rounding that the
     slightly different FP32 value sends to the neighbouring BF16 number
     (probability ~1e-6 / 2^-9 per operand, each a 2^-8 change of one term):
-    ~1e-4 relative L2.  Gate 1e-3 per tensor, for the whole loss and for each
+    ~1e-4 relative L2 (measured 1e-5 to 2e-4).  Gate 1e-3 per tensor, for the whole loss and for each
     of its three terms alone (loss weights (1,0,0), (0,1,0), (0,0,1)), so a
     dropped G or L contribution cannot hide behind the V term.  The gap to
     the exact FP64 reverse pass (the cost of BF16 operands) is reported."""
@@ -142,6 +142,10 @@ def test_gradient_matches_oracle(torch, q, oracle, small_table):
         assert abs(lg - lem) <= 1e-4 * lem
         for name, lo, hi in (("W1", lay.W1, lay.b1), ("b1", lay.b1, lay.W2), ("W2", lay.W2, lay.b2),
                              ("b2", lay.b2, lay.W3), ("W3", lay.W3, lay.b3), ("b3", lay.b3, lay.n_params)):
+            if not np.any(gem[name]):  # b3 has no part in the G or L terms: exactly zero
+                _say("  grad %s: zero in the oracle, max |gpu| %.3g" % (name, np.abs(g[lo:hi]).max()))
+                assert not np.any(g[lo:hi]), (case, name)
+                continue
             e_em = _rel_l2(g[lo:hi], gem[name].ravel())
             e_64 = _rel_l2(g[lo:hi], g64[name].ravel())
             _say("  grad %s rel L2 vs BF16 model %.3e (vs FP64 %.3e)" % (name, e_em, e_64))
