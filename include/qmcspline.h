@@ -162,6 +162,21 @@ int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
                            void* workspace_dev, size_t workspace_bytes, void* stream);
 int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
                          size_t workspace_bytes, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * spline_eval_vgl_sorted without a workspace argument.  Its scratch is a
+ * static device array of 6.4 MB (the sort of up to 524288 positions), one
+ * copy per GPU, created with the library's code object and held until the
+ * process ends; its address is looked up on the first call on each device
+ * (hipGetSymbolAddress, outside any capture the first time).  No hipMalloc,
+ * hipFree or other allocating call.  B > 524288 gives SPL_ENOMEM; B == 0 is
+ * a no-op.  Results equal spline_eval_vgl_sorted's bit for bit.  Every call
+ * on one GPU shares that GPU's array: the bucket counts are cleared by a
+ * kernel at the start of each call and the rest is overwritten before it is
+ * read, but calls that overlap on one GPU (other streams, other host
+ * threads) race on it. */
+int spline_eval_vgl_sorted_noalloc(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                                   void* stream);
 /* spline_eval_vgh in locality order (same arguments and results, bit for
  * bit), with the workspace above.  Its shape: 16-lane groups with the widest
  * chunk compiled for the storage type where it fits the row (else the

@@ -64,6 +64,7 @@ def lib():
             "spline_eval_v": ([p, p, i64, p, p], ctypes.c_int),
             "spline_sorted_workspace_bytes": ([p, i64], sz),
             "spline_eval_vgl_sorted": ([p, p, i64, p, p, p, p, sz, p], ctypes.c_int),
+            "spline_eval_vgl_sorted_noalloc": ([p, p, i64, p, p, p, p], ctypes.c_int),
             "spline_eval_v_sorted": ([p, p, i64, p, p, sz, p], ctypes.c_int),
             "spline_eval_ratio_vgl_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
             "spline_eval_ratio_v_sorted": ([p, p, i64, p, i64, p, p, p, sz, p], ctypes.c_int),
@@ -364,6 +365,19 @@ class Spline:
             check(lib().spline_eval_vgl_sorted(self._h, ctypes.c_void_p(pos.data_ptr()), B,
                                                ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
                                                ctypes.c_void_p(L.data_ptr()), wp, wn, sp))
+        return V, G, L
+
+    def eval_vgl_sorted_noalloc(self, pos, out, stream=None):
+        """eval_vgl_sorted through the entry point that allocates nothing (its
+        scratch is the library's static device array); out: caller's (V, G, L)."""
+        pos = self._pos(pos)
+        B = pos.shape[0]
+        V, G, L = self._vgl_out(out, B)
+        with self._torch.cuda.device(self.device):
+            sp, _ = _stream_ptr(self._torch, self.device, stream)
+            check(lib().spline_eval_vgl_sorted_noalloc(self._h, ctypes.c_void_p(pos.data_ptr()), B,
+                                                       ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                                       ctypes.c_void_p(L.data_ptr()), sp))
         return V, G, L
 
     def set_sorted_tile(self, tile):

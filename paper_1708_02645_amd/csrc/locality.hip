@@ -18,6 +18,7 @@
 #include <cstring>
 #include <fstream>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -242,6 +243,37 @@ static int sorted_common(const spline_s* s, const double* pos, int64_t B, void* 
     return sorted_run(s, vgl ? s->stile : s->svtile, vgl, pos, B, V, G, L, ws, st);
 }
 
+// Scratch of the entry point that allocates nothing: the sort's bucket
+// counts, keys, ranks and index list for up to kStaticMaxPositions
+// positions, one copy on every GPU the library runs on, held until the
+// process ends.  In host code `scratch` names a host-side stand-in; its
+// device address on the current GPU comes from hipGetSymbolAddress, looked
+// up once per device and kept in g_scratch_dev.
+constexpr int64_t kStaticMaxPositions = int64_t(1) << 19;
+constexpr size_t kStaticWords = (size_t)kLocBuckets + 3 * (size_t)kStaticMaxPositions;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) int32_t scratch[kStaticWords];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+static int static_scratch(void** out)
+{
+    int dev = -1;
+    QS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPL_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return fail(SPL_EHIP, "static scratch not 256-byte aligned");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return SPL_OK;
+}
+
 }  // namespace qs
 
 using namespace qs;
@@ -258,6 +290,18 @@ int spline_eval_vgl_sorted(const spline_t* s, const double* pos_dev, int64_t B, 
                            void* workspace_dev, size_t workspace_bytes, void* stream)
 {
     return sorted_common(s, pos_dev, B, V, G, L, workspace_dev, workspace_bytes, stream, true);
+}
+
+int spline_eval_vgl_sorted_noalloc(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
+                                   void* stream)
+{
+    if (B > kStaticMaxPositions)
+        return fail(SPL_ENOMEM, "B exceeds the static scratch of the no-allocation entry point (524288 positions)");
+    if (!s || B <= 0) return sorted_check(s, pos_dev, B, V, G, L, nullptr, 0, true);
+    void* ws = nullptr;
+    int rc = static_scratch(&ws);
+    if (rc) return rc;
+    return sorted_common(s, pos_dev, B, V, G, L, ws, kStaticWords * sizeof(int32_t), stream, true);
 }
 
 int spline_eval_v_sorted(const spline_t* s, const double* pos_dev, int64_t B, void* V, void* workspace_dev,
