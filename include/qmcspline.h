@@ -79,10 +79,12 @@ typedef struct spline_s spline_t;
  * any cell is contiguous in z and needs no modulo.  A row holds the orbitals
  * of one grid point, orbital fastest, zero-padded to row_bytes. */
 typedef struct {
-    int64_t row_bytes;      /* bytes per grid point (multiple of 256) */
+    int64_t row_bytes;      /* bytes per grid point: a multiple of 256 when the
+                               orbitals take more than 256 B, else of 64 (of 128
+                               for FP64) */
     int64_t n_pad;          /* orbitals per row including zero padding */
     int64_t table_bytes;    /* rows * row_bytes, at offset 0 of the buffer */
-    int64_t scales_offset;  /* byte offset of float scales[n_pad] */
+    int64_t scales_offset;  /* byte offset of float scales[n_pad] (256-byte aligned) */
     int64_t total_bytes;    /* what spline_table_bytes returns */
     int32_t elem_bytes;     /* 8, 4, 2, 2 */
     int32_t padded[3];      /* n[d] + 3 */

@@ -890,6 +890,14 @@ class SurrogateMLP:
         check(_mlp_lib().spline_mlp_get_info(self._h, ctypes.byref(st), ctypes.byref(nb)))
         return {"step": st.value, "bins_per_dim": nb.value}
 
+    def bin_errors(self):
+        """The error map as a float32 numpy array [nb, nb, nb] (bins along x,
+        y, z of the fractional position), copied from the state buffer."""
+        nb = self.info()["bins_per_dim"]
+        lay = self.layout
+        raw = self.buf[lay.bin_err:lay.bin_err + 4 * nb ** 3].cpu().numpy()
+        return raw.view(np.float32).reshape(nb, nb, nb).copy()
+
     def params_numpy(self):
         """Parameters as float64 numpy arrays in the oracle's dictionary form."""
         lay = self.layout

@@ -16,14 +16,14 @@
     X(ST, 2, 1, 64) X(ST, 2, 2, 64) X(ST, 2, 3, 64) X(ST, 3, 1, 64) X(ST, 3, 2, 64)        \
     X(ST, 4, 1, 64) X(ST, 4, 2, 64) X(ST, 1, 2, 32) X(ST, 2, 1, 32) X(ST, 2, 2, 32)        \
     X(ST, 3, 1, 32) X(ST, 4, 1, 32) X(ST, 4, 2, 32) X(ST, 2, 1, 16) X(ST, 4, 1, 16)        \
-    X(ST, 4, 2, 16)
+    X(ST, 4, 2, 16) X(ST, 1, 1, 16) X(ST, 3, 1, 16)
 
 // BF16 and FP16
 #define QS_SHAPES_16(X, ST)                                                               \
     X(ST, 1, 1, 64) X(ST, 1, 2, 64) X(ST, 1, 3, 64) X(ST, 2, 1, 64) X(ST, 2, 2, 64)        \
     X(ST, 2, 3, 64) X(ST, 3, 1, 64) X(ST, 3, 2, 64) X(ST, 4, 1, 64) X(ST, 2, 1, 32)        \
     X(ST, 3, 1, 32) X(ST, 4, 1, 32) X(ST, 4, 2, 32) X(ST, 2, 1, 16) X(ST, 4, 1, 16)        \
-    X(ST, 4, 2, 16)
+    X(ST, 4, 2, 16) X(ST, 1, 1, 16) X(ST, 3, 1, 16)
 
 #define QS_EVAL_VARIANTS(ST, CW, NCH, LPP)                                                \
     {ST, CW, NCH, LPP, true, false, (const void*)&eval_kernel<ST, CW, NCH, LPP, true>,     \

@@ -106,7 +106,13 @@ static int compute_layout(const spline_grid* g, int32_t n_orb, spline_dtype stor
     }
     int64_t row = 0;
     if (!mul_ok((int64_t)n_orb, es, &row)) return fail(SPL_ENOMEM, "row size overflow");
-    row = (row + 255) / 256 * 256;
+    // Rows longer than 256 B are padded to a multiple of 256 B.  Shorter rows
+    // (a few orbitals per GPU, e.g. one share of an orbital split) are padded
+    // only to the narrowest tile compiled for the storage type: 64 B (16
+    // lanes x one word), 128 B for FP64 (16 lanes x one double), so a 192-B
+    // row is not read as 256 B.
+    const int64_t gran = row > 256 ? 256 : (store == SPL_F64 ? 128 : 64);
+    row = (row + gran - 1) / gran * gran;
     int64_t rows = 1;
     for (int d = 0; d < 3; ++d)
         if (!mul_ok(rows, (int64_t)g->n[d] + 3, &rows)) return fail(SPL_ENOMEM, "table size overflow");
@@ -116,12 +122,14 @@ static int compute_layout(const spline_grid* g, int32_t n_orb, spline_dtype stor
     int64_t sb = 0;
     if (!mul_ok(n_pad, 4, &sb)) return fail(SPL_ENOMEM, "scale size overflow");
     sb = (sb + 255) / 256 * 256;
-    if (tb > std::numeric_limits<int64_t>::max() - sb) return fail(SPL_ENOMEM, "table size overflow");
+    if (tb > std::numeric_limits<int64_t>::max() - 256) return fail(SPL_ENOMEM, "table size overflow");
+    const int64_t so = (tb + 255) / 256 * 256;  // scales start on a 256-byte boundary
+    if (so > std::numeric_limits<int64_t>::max() - sb) return fail(SPL_ENOMEM, "table size overflow");
     L->row_bytes = row;
     L->n_pad = n_pad;
     L->table_bytes = tb;
-    L->scales_offset = tb;
-    L->total_bytes = tb + sb;
+    L->scales_offset = so;
+    L->total_bytes = so + sb;
     L->elem_bytes = es;
     for (int d = 0; d < 3; ++d) L->padded[d] = g->n[d] + 3;
     return SPL_OK;
@@ -219,7 +227,7 @@ int spline_pack_host(const spline_grid* grid, int32_t n_orb, const double* coefs
         }
     }
     float* sc = reinterpret_cast<float*>(out + L.scales_offset);
-    std::memset(out + L.scales_offset, 0, (size_t)(L.total_bytes - L.scales_offset));
+    std::memset(out + L.table_bytes, 0, (size_t)(L.total_bytes - L.table_bytes));  // gap before the scales too
     for (int64_t m = 0; m < L.n_pad; ++m) sc[m] = (float)scale[m];
 
     std::vector<double> inv(N);

@@ -192,11 +192,11 @@ int vgh_launch_indexed(const spline_s* s, const spline_tile& t, bool hessian, co
 // In locality order the rows of neighbouring positions come from cache and
 // the shape decides the speed (on the plain path, bound by HBM, the VGH
 // tuner's candidates are equal within noise, and its pick can be 20% slower
-// here): 16-lane groups with 16-byte (else 8-byte) chunks where they fit.
+// here): 16-lane groups with the widest chunk (16, 12, 8 or 4 bytes) that fits.
 spline_tile vgh_sorted_tile(const spline_s* s)
 {
     spline_tile t = s->htile;
-    for (int cw : {4, 2}) {
+    for (int cw : {4, 3, 2, 1}) {
         const spline_tile c{cw, 1, 16, t.pb};
         const VghVariant* v = find_vgh(s->store, c, VGH_OUT_H);
         if (v && vgh_fits(s, *v) && find_vgh(s->store, c, VGH_OUT_L)) {

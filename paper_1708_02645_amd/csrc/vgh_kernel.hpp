@@ -305,10 +305,11 @@ struct VghVariant {
     X(ST, 2, 1, 32) X(ST, 4, 1, 32) X(ST, 2, 1, 16) X(ST, 4, 1, 16)
 #define QS_VGH_SHAPES_F32(X, ST)                                                          \
     X(ST, 1, 1, 64) X(ST, 1, 2, 64) X(ST, 2, 1, 64) X(ST, 1, 3, 64) X(ST, 3, 1, 64)        \
-    X(ST, 4, 1, 64) X(ST, 2, 1, 32) X(ST, 4, 1, 32) X(ST, 2, 1, 16) X(ST, 4, 1, 16)
+    X(ST, 4, 1, 64) X(ST, 2, 1, 32) X(ST, 4, 1, 32) X(ST, 2, 1, 16) X(ST, 4, 1, 16)        \
+    X(ST, 1, 1, 16) X(ST, 3, 1, 16)
 #define QS_VGH_SHAPES_16(X, ST)                                                           \
     X(ST, 1, 1, 64) X(ST, 1, 2, 64) X(ST, 2, 1, 64) X(ST, 1, 1, 32) X(ST, 2, 1, 32)        \
-    X(ST, 1, 1, 16) X(ST, 2, 1, 16)
+    X(ST, 1, 1, 16) X(ST, 2, 1, 16) X(ST, 3, 1, 16)
 
 #define QS_VGH_VARIANTS(ST, CW, NCH, LPP)                                                 \
     {ST, CW, NCH, LPP, VGH_OUT_H, (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_H>,   \

@@ -41,8 +41,21 @@ def test_layout_and_sizes():
     L = q.get_layout((16, 16, 16), 32, "f64")
     assert L.row_bytes == 256 and L.n_pad == 32
     L = q.get_layout((5, 6, 7), 37, "bf16")
-    assert L.row_bytes == 256 and L.n_pad == 128
+    assert L.row_bytes == 128 and L.n_pad == 64
     assert q.table_bytes((5, 6, 7), 37, "bf16") == L.total_bytes
+    # rows of at most 256 B pad to 64 B (128 B for FP64), longer rows to 256 B;
+    # the scales start on a 256-byte boundary after the table
+    for grid, n, dt, row in (((80, 80, 80), 48, "f32", 192), ((8, 8, 8), 40, "f32", 192),
+                             ((8, 8, 8), 24, "f32", 128), ((8, 8, 8), 16, "f32", 64),
+                             ((8, 8, 8), 24, "f64", 256), ((8, 8, 8), 8, "f64", 128),
+                             ((8, 8, 8), 100, "f32", 512), ((8, 8, 8), 96, "f16", 192),
+                             ((8, 8, 8), 130, "bf16", 512)):
+        L = q.get_layout(grid, n, dt)
+        assert L.row_bytes == row, (grid, n, dt, L.row_bytes)
+        assert L.n_pad * L.elem_bytes == row
+        assert L.table_bytes == (grid[0] + 3) * (grid[1] + 3) * (grid[2] + 3) * row
+        assert L.scales_offset % 256 == 0 and 0 <= L.scales_offset - L.table_bytes < 256
+        assert L.total_bytes == L.scales_offset + (4 * L.n_pad + 255) // 256 * 256
 
 
 @pytest.mark.parametrize("args", [
