@@ -485,8 +485,12 @@ int spline_mlp_select_frequencies(const spline_grid* grid, int32_t n_orb, const 
 /* Byte offsets inside the parameter buffer (all 256-byte aligned), and the
  * element offsets of each tensor inside the flat FP32 parameter vector
  * [W1 (256x96) | b1 | W2 (256x256) | b2 | W3 (Nx256) | b3], weights stored
- * [out][in].  The buffer is the whole network state: copying it is a
- * checkpoint, and spline_mlp_attach resumes from one. */
+ * [out][in].  weights_bf16 holds the BF16 copies of W1, W2, W3 that the
+ * evaluation reads, each in matrix-core fragment order: fragment (b, t),
+ * rows 16b..16b+15 and columns 32t..32t+31, is 512 consecutive values (b
+ * major), row 16b+c, columns 32t+8g..32t+8g+7 at 8(16g+c).  The buffer is
+ * the whole network state: copying it is a checkpoint, and spline_mlp_attach
+ * resumes from one. */
 typedef struct {
     int64_t n_params;
     int64_t W1, b1, W2, b2, W3, b3;

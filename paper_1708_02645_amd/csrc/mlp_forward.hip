@@ -1,23 +1,26 @@
 // Fused forward-mode evaluation of the surrogate network on the matrix cores
 // (gfx950, v_mfma_f32_16x16x32_bf16, BF16 operands, FP32 accumulation).
 //
-// One wave evaluates 16 positions through all layers.  Operand layout of
-// the instruction (lane l, g = l/16, c = l%16): A[c][8g..8g+7],
-// B[8g..8g+7][c], C[4g..4g+3][c].  Each layer is computed transposed,
-// H^T[unit][pos] = sum_k W[unit][k] Act[pos][k]: the weight rows are the A
-// operand (read from global memory, 280 KB in all, L2-resident) and the
-// layer input, held in registers for all K, is the B operand.  Each stream
-// (value, d/dx, d/dy, d/dz, Laplacian) is its own product, so the five
-// accumulators of a (unit, position) pair sit in the same lane and slot and
-// the forward-mode SiLU combines them in registers.  A lane then holds four
-// consecutive units of one position, which it writes to LDS with one 8-byte
-// store per stream (a [stream][16][256] BF16 tile, 16-byte chunks XOR-swizzled
-// by row), to be read back as the next layer's B operands.
-//
-// Output units are processed in groups of 64 with two accumulator sets: the
-// epilogue of group k follows the first products of group k+1, so the vector
-// ALU work of one overlaps the matrix-core work of the other, and weight
-// fragments are loaded four steps ahead of their use.
+// A workgroup of four waves evaluates 16 positions through all layers; wave
+// w owns a quarter of every layer's output units (64 of a hidden layer's
+// 256).  Operand layout of the instruction (lane l, g = l/16, c = l%16):
+// A[c][8g..8g+7], B[8g..8g+7][c], C[4g..4g+3][c].  Each layer is computed
+// transposed, H^T[unit][pos] = sum_k W[unit][k] Act[pos][k]:
+//  - weight rows are the A operand, read from global memory a few K steps
+//    ahead of use (280 KB in all, L2-resident).  The BF16 weights are kept
+//    in fragment order, so one wave's operand load is one contiguous 1 KB
+//    block; row-major rows made it 16 half-used cache lines, and those loads
+//    were the kernel's bound;
+//  - the layer input, a [stream][16][256] BF16 tile in LDS shared by the
+//    four waves (16-byte chunks XOR-swizzled by row), gives the B operands,
+//    read one K step ahead.
+// Each stream (value, d/dx, d/dy, d/dz, Laplacian) is its own product, so
+// the five accumulators of a (unit, position) pair sit in the same lane and
+// slot and the forward-mode SiLU combines them in registers; a lane then
+// holds four consecutive units of one position and writes them to the other
+// tile with one 8-byte store per stream.  Two tiles alternate as layer input
+// and output (80 KB per workgroup), so two workgroups share a CU: two waves
+// per SIMD, one's vector work hiding behind the other's matrix products.
 #include "mlp_kernels.hpp"
 
 #include "common.hpp"
@@ -26,216 +29,271 @@ namespace qs {
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
+constexpr int kFwdWaves = 4;
+constexpr int kFwdPos = 16;
+constexpr int kTile = kStreams * kFwdPos * kHidden;  // BF16 elements of one activation tile
+
+// Element offset of (stream s, position row, column col) in a tile: 16-byte
+// chunks XOR-swizzled by the row, so the 16 rows a wave reads or writes at
+// one column fall in distinct banks.
 __device__ inline int zoff(int s, int row, int col)
 {
-    return ((s * 16 + row) * kHidden + ((((col >> 3) ^ (row & 7)) << 3) | (col & 7)));
+    return ((s * kFwdPos + row) * kHidden + ((((col >> 3) ^ (row & 15)) << 3) | (col & 7)));
 }
 
-// A layer of NCG groups of 64 output units (4 blocks of 16) over KSTEPS
-// steps of 32 inputs, as one unrolled sequence of NCG*KSTEPS steps; `blocks`
-// clamps the weight rows of a partial last group (never stored).  The
-// weight fragments of step i+4 are loaded while step i runs (a ring of five,
-// across group boundaries), and the epilogue of group k is placed after the
-// first products of group k+1 (two accumulator sets), so that loads, matrix
-// products and vector work of neighbouring groups overlap.
-template <int KSTEPS, int NCG, class Epi>
-__device__ inline void layer(const bf16x8 (&X)[kStreams][KSTEPS], const __bf16* __restrict__ W, int blocks, int g,
-                             int c, const Epi& epi)
+// acc[s][nb] = sum over KSTEPS*32 inputs of W[(blk0+nb)*16 + unit][k] xt[s][pos][k]
+// for NB blocks of 16 units; `blocks` clamps the weight rows of blocks past
+// the layer's end (their results are never used).
+template <int KSTEPS, int NB>
+__device__ inline void layer_products(const __bf16* __restrict__ xt, const __bf16* __restrict__ W, int blk0,
+                                      int blocks, int g, int c, f32x4 (&acc)[kStreams][NB])
 {
-    constexpr int K = 32 * KSTEPS;
-    constexpr int S = NCG * KSTEPS;
-    auto load = [&](int step, bf16x8 (&dst)[4]) {
-        const int cg = step / KSTEPS, t = step % KSTEPS;
+    constexpr int R = 4;  // ring depth: weight fragments of step t+R-1 are loaded at step t
+    // W is in fragment order: fragment (blk, t) is 512 values, lane l's 8 at 8l.
+    const __bf16* wrow[NB];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int blk = cg * 4 + nb < blocks ? cg * 4 + nb : blocks - 1;
-            dst[nb] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(blk * 16 + c) * K + 32 * t + 8 * g);
-        }
-    };
-    constexpr int R = 5;  // ring depth: fragments of step i+R-1 are loaded at step i
-    bf16x8 ring[R][4];
+    for (int nb = 0; nb < NB; ++nb) {
+        const int blk = blk0 + nb < blocks ? blk0 + nb : blocks - 1;
+        wrow[nb] = W + (int64_t)blk * KSTEPS * 512 + 8 * (16 * g + c);
+    }
+    bf16x8 ring[R][NB];
 #pragma unroll
     for (int i = 0; i < R - 1; ++i)
-        if (i < S) load(i, ring[i]);
-    f32x4 acc[2][kStreams][4];
-    // fully unrolled: every register-array index below must be a constant
-#pragma clang loop unroll(full)
-    for (int step = 0; step < S; ++step) {
-        const int cg = step / KSTEPS, t = step % KSTEPS;
-        if (step + R - 1 < S) load(step + R - 1, ring[(step + R - 1) % R]);
-        if (t == 0) {
+        if (i < KSTEPS)
 #pragma unroll
-            for (int s = 0; s < kStreams; ++s)
+            for (int nb = 0; nb < NB; ++nb) ring[i][nb] = *reinterpret_cast<const bf16x8*>(wrow[nb] + 512 * i);
+    bf16x8 x[2][kStreams];
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) acc[cg & 1][s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int s = 0; s < kStreams; ++s)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                acc[cg & 1][s][nb] =
-                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[step % R][nb], X[s][t], acc[cg & 1][s][nb], 0, 0, 0);
-        if (t == 0 && cg >= 1) epi(cg - 1, acc[(cg - 1) & 1]);
-    }
-    epi(NCG - 1, acc[(NCG - 1) & 1]);
-}
-
-// Hidden layer epilogue: bias, forward-mode SiLU, BF16 into the LDS tile.
-struct HiddenEpi {
-    const float* bias;
-    __bf16* zb;
-    int g, c;
-    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
-    {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int u0 = cg * 64 + nb * 16 + 4 * g;
-            const f32x4v b = *reinterpret_cast<const f32x4v*>(bias + u0);
-            __bf16 z[kStreams][4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float hv = acc[0][nb][j] + b[j];
-                const float hx = acc[1][nb][j], hy = acc[2][nb][j], hz = acc[3][nb][j], hl = acc[4][nb][j];
-                float d1, d2;
-                z[0][j] = (__bf16)silu3(hv, d1, d2);
-                z[1][j] = (__bf16)(d1 * hx);
-                z[2][j] = (__bf16)(d1 * hy);
-                z[3][j] = (__bf16)(d1 * hz);
-                z[4][j] = (__bf16)(d1 * hl + d2 * (hx * hx + hy * hy + hz * hz));
-            }
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s) {
-                uint64_t packed;
-                __builtin_memcpy(&packed, z[s], 8);
-                *reinterpret_cast<uint64_t*>(zb + zoff(s, c, u0)) = packed;
-            }
-        }
-    }
-};
-
-// Output epilogue: bias and the per-orbital affine map; 16-byte stores of
-// four consecutive orbitals of one position to V, G, L.
-struct OutEpi {
-    const MlpFwdArgs* a;
-    const float* b3;
-    int64_t b0;
-    int blocks, g, c;
-    __device__ void operator()(int cg, const f32x4 (&acc)[kStreams][4]) const
-    {
-        const int64_t b = b0 + c;
-        if (b >= a->B) return;
-        const int N = a->nout;
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            if (cg * 4 + nb >= blocks) continue;
-            const int n0 = (cg * 4 + nb) * 16 + 4 * g;
-            const f32x4v sd = *reinterpret_cast<const f32x4v*>(a->sd + n0);
-            const f32x4v mu = *reinterpret_cast<const f32x4v*>(a->mu + n0);
-            const f32x4v bb = *reinterpret_cast<const f32x4v*>(b3 + n0);
-            f32x4v v, gx, gy, gz, l;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                v[j] = (acc[0][nb][j] + bb[j]) * sd[j] + mu[j];
-                gx[j] = acc[1][nb][j] * sd[j];
-                gy[j] = acc[2][nb][j] * sd[j];
-                gz[j] = acc[3][nb][j] * sd[j];
-                l[j] = acc[4][nb][j] * sd[j];
-            }
-            *reinterpret_cast<f32x4v*>(a->V + b * N + n0) = v;
-            *reinterpret_cast<f32x4v*>(a->G + (3 * b + 0) * N + n0) = gx;
-            *reinterpret_cast<f32x4v*>(a->G + (3 * b + 1) * N + n0) = gy;
-            *reinterpret_cast<f32x4v*>(a->G + (3 * b + 2) * N + n0) = gz;
-            *reinterpret_cast<f32x4v*>(a->L + b * N + n0) = l;
-        }
-    }
-};
-
-__device__ inline void load_x(bf16x8 (&X)[kStreams][kHidden / 32], const __bf16* zb, int g, int c)
-{
+    for (int s = 0; s < kStreams; ++s) x[0][s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 8 * g));
 #pragma unroll
     for (int s = 0; s < kStreams; ++s)
 #pragma unroll
-        for (int t = 0; t < kHidden / 32; ++t)
-            X[s][t] = *reinterpret_cast<const bf16x8*>(zb + zoff(s, c, 32 * t + 8 * g));
+        for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // The scheduling fences keep each step's loads ahead of its products
+    // (otherwise the scheduler sinks them next to their use and every step
+    // waits for a full L2 or LDS round trip).
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < KSTEPS; ++t) {
+        if (t + R - 1 < KSTEPS)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                ring[(t + R - 1) % R][nb] = *reinterpret_cast<const bf16x8*>(wrow[nb] + 512 * (t + R - 1));
+        if (t + 1 < KSTEPS)
+#pragma unroll
+            for (int s = 0; s < kStreams; ++s)
+                x[(t + 1) & 1][s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 32 * (t + 1) + 8 * g));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < kStreams; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[t % R][nb], x[t & 1][s], acc[s][nb], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
-template <int NCG_OUT>
-__global__ __launch_bounds__(64) void mlp_vgl_kernel(MlpFwdArgs a)
+// Hidden layer epilogue: bias, forward-mode SiLU, BF16 into the output tile.
+template <int NB>
+__device__ inline void hidden_epilogue(const f32x4 (&acc)[kStreams][NB], const float* __restrict__ bias,
+                                       __bf16* zo, int blk0, int g, int c)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 zb[kStreams * 16 * kHidden];
-    const int l = threadIdx.x, g = l >> 4, c = l & 15;
-    const int64_t b0 = (int64_t)blockIdx.x * 16;
-    const MlpOffsets o = mlp_offsets(a.nout);
-
-    // Per-frequency constants, once per workgroup: the integer frequency and
-    // its Cartesian factors 2 pi k_d / cell_d and their squared norm.  They
-    // live at the start of the activation tile, which the first layer's
-    // epilogue overwrites only after the features are in registers (and
-    // after the barrier below), so the workgroup's LDS stays at one tile.
-    int32_t (*fk)[3] = reinterpret_cast<int32_t (*)[3]>(zb);
-    float (*fg)[4] = reinterpret_cast<float (*)[4]>(reinterpret_cast<unsigned char*>(zb) + kFreq * 3 * 4);
-    if (l < kFreq) {
-        float g2 = 0.f;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int k = a.freqs[3 * l + d];
-            fk[l][d] = k;
-            const float gd = (float)(6.283185307179586 * k / a.cell[d]);
-            fg[l][d] = gd;
-            g2 += gd * gd;
+    for (int nb = 0; nb < NB; ++nb) {
+        const int u0 = (blk0 + nb) * 16 + 4 * g;
+        const f32x4v b = *reinterpret_cast<const f32x4v*>(bias + u0);
+        __bf16 z[kStreams][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float hv = acc[0][nb][j] + b[j];
+            const float hx = acc[1][nb][j], hy = acc[2][nb][j], hz = acc[3][nb][j], hl = acc[4][nb][j];
+            float d1, d2;
+            z[0][j] = (__bf16)silu3(hv, d1, d2);
+            z[1][j] = (__bf16)(d1 * hx);
+            z[2][j] = (__bf16)(d1 * hy);
+            z[3][j] = (__bf16)(d1 * hz);
+            z[4][j] = (__bf16)(d1 * hl + d2 * (hx * hx + hy * hy + hz * hz));
         }
-        fg[l][3] = g2;
+#pragma unroll
+        for (int s = 0; s < kStreams; ++s) {
+            uint64_t packed;
+            __builtin_memcpy(&packed, z[s], 8);
+            *reinterpret_cast<uint64_t*>(zo + zoff(s, c, u0)) = packed;
+        }
     }
-    __syncthreads();
+}
 
-    // Layer-1 operands: the features of position b0 + c.  Phase k.u reduced
-    // modulo 1 in FP64; the hardware sine/cosine take revolutions.
-    int64_t bi = b0 + c;
+// Output epilogue: bias and the per-orbital affine map.  STAGED: the
+// workgroup's outputs (16 positions of V, G and L, 80 rows of nout floats)
+// are first written to LDS, rows padded by 4 floats so a wave's 16 rows fall
+// in distinct banks, then copied to V, G, L as contiguous 16-byte stores (the
+// 16 positions' rows of each output are contiguous in memory).  Otherwise
+// each lane stores four consecutive orbitals of one position directly.
+constexpr int kStagePad = 4;
+
+__device__ inline int stage_row(int q, int pos, int nout)
+{
+    // q: 0 value, 1..3 gradient components, 4 Laplacian
+    return q == 0 ? pos : (q == 4 ? 4 * kFwdPos + pos : kFwdPos + 3 * pos + (q - 1));
+}
+
+template <int NB, bool STAGED>
+__device__ inline void output_epilogue(const MlpFwdArgs& a, const f32x4 (&acc)[kStreams][NB], const float* b3,
+                                       int64_t b0, int blk0, int blocks, int g, int c, float* stage)
+{
+    const int N = a.nout;
+    const int64_t b = b0 + c;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        if (blk0 + nb >= blocks) continue;
+        const int n0 = (blk0 + nb) * 16 + 4 * g;
+        const f32x4v sd = *reinterpret_cast<const f32x4v*>(a.sd + n0);
+        const f32x4v mu = *reinterpret_cast<const f32x4v*>(a.mu + n0);
+        const f32x4v bb = *reinterpret_cast<const f32x4v*>(b3 + n0);
+        f32x4v q[kStreams];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            q[0][j] = (acc[0][nb][j] + bb[j]) * sd[j] + mu[j];
+#pragma unroll
+            for (int s = 1; s < kStreams; ++s) q[s][j] = acc[s][nb][j] * sd[j];
+        }
+        if constexpr (STAGED) {
+#pragma unroll
+            for (int s = 0; s < kStreams; ++s)
+                *reinterpret_cast<f32x4v*>(stage + stage_row(s, c, N) * (N + kStagePad) + n0) = q[s];
+        } else {
+            if (b >= a.B) continue;
+            __builtin_nontemporal_store(q[0], reinterpret_cast<f32x4v*>(a.V + b * N + n0));
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                __builtin_nontemporal_store(q[1 + d], reinterpret_cast<f32x4v*>(a.G + (3 * b + d) * N + n0));
+            __builtin_nontemporal_store(q[4], reinterpret_cast<f32x4v*>(a.L + b * N + n0));
+        }
+    }
+}
+
+// Copies the staged outputs of positions [b0, b0 + np) to V, G, L: the
+// workgroup's rows of each output are one contiguous run in memory, walked in
+// 16-byte pieces by consecutive threads.
+__device__ inline void store_staged(const MlpFwdArgs& a, const float* stage, int64_t b0, int np, int tid)
+{
+    const int N = a.nout, n4 = N / 4;
+    const int per = np * n4;  // 16-byte pieces per value row block
+    // value rows (np), gradient rows (3 np), Laplacian rows (np)
+    for (int i = tid; i < 5 * per; i += kFwdWaves * 64) {
+        int r, k, srow;
+        float* dst;
+        if (i < per) {
+            r = i / n4, k = i - r * n4, srow = r;
+            dst = a.V + (b0 + r) * N;
+        } else if (i < 4 * per) {
+            const int j = i - per;
+            r = j / n4, k = j - r * n4, srow = kFwdPos + r;
+            dst = a.G + (3 * b0 + r) * N;
+        } else {
+            const int j = i - 4 * per;
+            r = j / n4, k = j - r * n4, srow = 4 * kFwdPos + r;
+            dst = a.L + (b0 + r) * N;
+        }
+        const f32x4v v = *reinterpret_cast<const f32x4v*>(stage + srow * (N + kStagePad) + 4 * k);
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(dst + 4 * k));
+    }
+}
+
+// Features of the workgroup's 16 positions into tile zt: thread t < 192
+// takes position t/12 and the 8 feature columns 8(t%12)..+7 (sin for columns
+// below kFreq, cos above), five streams each, one 16-byte store per stream.
+// The phase k.u is reduced modulo 1 in FP64; the hardware sine/cosine take
+// the angle in revolutions.
+__device__ inline void stage_features(const MlpFwdArgs& a, int64_t b0, int tid, __bf16* zt)
+{
+    if (tid >= kFwdPos * (kIn / 8)) return;
+    const int p = tid / (kIn / 8), ch = tid % (kIn / 8);
+    int64_t bi = b0 + p;
     if (bi >= a.B) bi = a.B - 1;  // ragged tail: computed, never stored
     double u[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = a.pos[3 * bi + d] * (1.0 / a.cell[d]);
-    bf16x8 X1[kStreams][3];
+    for (int d = 0; d < 3; ++d) u[d] = a.pos[3 * bi + d] * a.icell[d];
+    bf16x8 f[kStreams];
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
+    for (int j = 0; j < 8; ++j) {
+        const int k = 8 * ch + j;
+        const int fi = k < kFreq ? k : k - kFreq;
+        const int kx = a.freqs[3 * fi], ky = a.freqs[3 * fi + 1], kz = a.freqs[3 * fi + 2];
+        double x = (double)kx * u[0] + (double)ky * u[1] + (double)kz * u[2];
+        x -= floor(x);
+        const float sn = __builtin_amdgcn_sinf((float)x), cs = __builtin_amdgcn_cosf((float)x);
+        const float gx = (float)(kx * a.tpc[0]), gy = (float)(ky * a.tpc[1]), gz = (float)(kz * a.tpc[2]);
+        const float val = k < kFreq ? sn : cs, dv = k < kFreq ? cs : -sn;
+        f[0][j] = (__bf16)val;
+        f[1][j] = (__bf16)(dv * gx);
+        f[2][j] = (__bf16)(dv * gy);
+        f[3][j] = (__bf16)(dv * gz);
+        f[4][j] = (__bf16)(-(gx * gx + gy * gy + gz * gz) * val);
+    }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 32 * t + 8 * g + j;
-            const int fi = k < kFreq ? k : k - kFreq;
-            double x = (double)fk[fi][0] * u[0] + (double)fk[fi][1] * u[1] + (double)fk[fi][2] * u[2];
-            x -= floor(x);
-            const float sn = __builtin_amdgcn_sinf((float)x), cs = __builtin_amdgcn_cosf((float)x);
-            const float val = k < kFreq ? sn : cs, dv = k < kFreq ? cs : -sn;
-            X1[0][t][j] = (__bf16)val;
-            X1[1][t][j] = (__bf16)(dv * fg[fi][0]);
-            X1[2][t][j] = (__bf16)(dv * fg[fi][1]);
-            X1[3][t][j] = (__bf16)(dv * fg[fi][2]);
-            X1[4][t][j] = (__bf16)(-fg[fi][3] * val);
-        }
+    for (int s = 0; s < kStreams; ++s) *reinterpret_cast<bf16x8*>(zt + zoff(s, p, 8 * ch)) = f[s];
+}
 
-    __syncthreads();  // every lane's features are in registers before the tile is written
-    layer<3, kHidden / 64>(X1, a.Wh + o.hW1, kHidden / 16, g, c, HiddenEpi{a.P + o.b1, zb, g, c});
+// NBO: output blocks of 16 orbitals per wave, ceil(nout / 64).  STAGED:
+// outputs go through LDS (needs 80 (nout + 4) floats, within the two tiles).
+template <int NBO, bool STAGED>
+__global__ __launch_bounds__(kFwdWaves * 64) void mlp_vgl_kernel(MlpFwdArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 tiles[2 * kTile];
+    __bf16* t0 = tiles;
+    __bf16* t1 = tiles + kTile;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+    const int64_t b0 = (int64_t)blockIdx.x * kFwdPos;
+    const MlpOffsets o = mlp_offsets(a.nout);
+    constexpr int NBH = kHidden / 16 / kFwdWaves;  // hidden blocks per wave
+
+    stage_features(a, b0, tid, t0);
     __syncthreads();
-    bf16x8 X[kStreams][kHidden / 32];
-    load_x(X, zb, g, c);
+    {
+        f32x4 acc[kStreams][NBH];
+        layer_products<kIn / 32, NBH>(t0, a.Wh + o.hW1, NBH * w, kHidden / 16, g, c, acc);
+        hidden_epilogue<NBH>(acc, a.P + o.b1, t1, NBH * w, g, c);
+    }
     __syncthreads();
-    layer<kHidden / 32, kHidden / 64>(X, a.Wh + o.hW2, kHidden / 16, g, c, HiddenEpi{a.P + o.b2, zb, g, c});
+    {
+        f32x4 acc[kStreams][NBH];
+        layer_products<kHidden / 32, NBH>(t1, a.Wh + o.hW2, NBH * w, kHidden / 16, g, c, acc);
+        hidden_epilogue<NBH>(acc, a.P + o.b2, t0, NBH * w, g, c);
+    }
     __syncthreads();
-    load_x(X, zb, g, c);
     const int nblk = a.nout / 16;
-    layer<kHidden / 32, NCG_OUT>(X, a.Wh + o.hW3, nblk, g, c, OutEpi{&a, a.P + o.b3, b0, nblk, g, c});
+    f32x4 acc[kStreams][NBO];
+    layer_products<kHidden / 32, NBO>(t0, a.Wh + o.hW3, NBO * w, nblk, g, c, acc);
+    float* stage = reinterpret_cast<float*>(tiles);
+    if constexpr (STAGED) __syncthreads();  // every wave has read its last operands from t0
+    output_epilogue<NBO, STAGED>(a, acc, a.P + o.b3, b0, NBO * w, nblk, g, c, stage);
+    if constexpr (STAGED) {
+        __syncthreads();
+        const int64_t left = a.B - b0;
+        store_staged(a, stage, b0, left < kFwdPos ? (int)left : kFwdPos, tid);
+    }
 }
 
 int launch_mlp_forward(const MlpFwdArgs& a, hipStream_t st)
 {
-    const int64_t blocks = (a.B + 15) / 16;
+    const int64_t blocks = (a.B + kFwdPos - 1) / kFwdPos;
     if (blocks > 0x7fffffff) return fail(SPL_EINVAL, "batch too large");
-    const int ncg = (a.nout / 16 + 3) / 4;
-    switch (ncg) {
-    case 1: hipLaunchKernelGGL(mlp_vgl_kernel<1>, dim3((unsigned)blocks), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(mlp_vgl_kernel<2>, dim3((unsigned)blocks), dim3(64), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(mlp_vgl_kernel<3>, dim3((unsigned)blocks), dim3(64), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(mlp_vgl_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, st, a); break;
+    if (a.nout < 16 || a.nout > kMaxOut || a.nout % 16) return fail(SPL_EUNSUPPORTED, "output width out of range");
+    for (const float* p : {a.V, a.G, a.L})
+        if (reinterpret_cast<uintptr_t>(p) & 15) return fail(SPL_EINVAL, "V, G and L must be 16-byte aligned");
+    const int nbo = (a.nout / 16 + kFwdWaves - 1) / kFwdWaves;
+    const bool staged = (size_t)5 * kFwdPos * (a.nout + kStagePad) * sizeof(float) <= 2 * kTile * sizeof(__bf16);
+    const dim3 grid((unsigned)blocks), block(kFwdWaves * 64);
+    switch (nbo * 2 + (staged ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((mlp_vgl_kernel<1, false>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((mlp_vgl_kernel<1, true>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((mlp_vgl_kernel<2, false>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((mlp_vgl_kernel<2, true>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((mlp_vgl_kernel<3, false>), grid, block, 0, st, a); break;
+    case 7: hipLaunchKernelGGL((mlp_vgl_kernel<3, true>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((mlp_vgl_kernel<4, false>), grid, block, 0, st, a); break;
+    case 9: hipLaunchKernelGGL((mlp_vgl_kernel<4, true>), grid, block, 0, st, a); break;
     default: return fail(SPL_EUNSUPPORTED, "output width out of range");
     }
     QS_HIP(hipGetLastError());

@@ -23,8 +23,8 @@ __global__ void mlp_loss_kernel(const float*, const float*, const float*, const 
 __global__ void mlp_bias_grad_kernel(const float*, int64_t, int, float*);
 __global__ void splitk_reduce_kernel(const float*, int, int64_t, int64_t, float*);
 __global__ void adam_kernel(float*, const float*, float*, float*, int64_t, float, float, float, float, float, float,
-                            __bf16*);
-__global__ void bf16_copy_kernel(const float*, __bf16*, int64_t);
+                            __bf16*, int32_t);
+__global__ void bf16_copy_kernel(const float*, __bf16*, int64_t, int32_t);
 __global__ void mlp_stats_kernel(const float*, const float*, const float*, int64_t, int, double*);
 __global__ void colmax_kernel(const float*, const float*, const float*, int64_t, int, unsigned int*);
 __global__ void bin_error_kernel(const double*, double, double, double, int, const float*, const float*, const float*,
@@ -155,7 +155,11 @@ static MlpFwdArgs fwd_args(const spline_mlp_s* m, const double* pos, int64_t B, 
     a.pos = pos;
     a.B = B;
     a.freqs = reinterpret_cast<const int32_t*>(m->dev + m->lay.freqs);
-    for (int d = 0; d < 3; ++d) a.cell[d] = m->cell[d];
+    for (int d = 0; d < 3; ++d) {
+        a.cell[d] = m->cell[d];
+        a.icell[d] = 1.0 / m->cell[d];
+        a.tpc[d] = 6.283185307179586 / m->cell[d];
+    }
     a.Wh = reinterpret_cast<const __bf16*>(m->dev + m->lay.Wh);
     a.P = reinterpret_cast<const float*>(m->dev + m->lay.P);
     a.mu = reinterpret_cast<const float*>(m->dev + m->lay.mu);
@@ -371,9 +375,12 @@ int spline_mlp_create(const spline_mlp_desc* desc, const int32_t* freqs_host, co
     }
     const float* P = reinterpret_cast<const float*>(D + m->lay.P);
     __bf16* Wh = reinterpret_cast<__bf16*>(D + m->lay.Wh);
-    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b1)), dim3(kThreads), 0, st, P + m->o.W1, Wh + m->o.hW1, m->o.b1 - m->o.W1);
-    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b2 - m->o.W2)), dim3(kThreads), 0, st, P + m->o.W2, Wh + m->o.hW2, m->o.b2 - m->o.W2);
-    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b3 - m->o.W3)), dim3(kThreads), 0, st, P + m->o.W3, Wh + m->o.hW3, m->o.b3 - m->o.W3);
+    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b1)), dim3(kThreads), 0, st, P + m->o.W1, Wh + m->o.hW1,
+                       m->o.b1 - m->o.W1, kIn);
+    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b2 - m->o.W2)), dim3(kThreads), 0, st, P + m->o.W2,
+                       Wh + m->o.hW2, m->o.b2 - m->o.W2, kHidden);
+    hipLaunchKernelGGL(bf16_copy_kernel, dim3(grid1(m->o.b3 - m->o.W3)), dim3(kThreads), 0, st, P + m->o.W3,
+                       Wh + m->o.hW3, m->o.b3 - m->o.W3, kHidden);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid1(kMaxBins * kMaxBins * kMaxBins)), dim3(kThreads), 0, st,
                        reinterpret_cast<unsigned int*>(D + m->lay.bin_err), 0x7f800000u,
                        (int64_t)kMaxBins * kMaxBins * kMaxBins);  // no map yet: every bin routes to the spline
@@ -512,11 +519,14 @@ int spline_mlp_train_step(spline_mlp_t* m, const double* pos, const float* tV, c
     const MlpOffsets& o = m->o;
     struct Seg {
         int64_t p, n, h;
-    } segs[6] = {{o.W1, o.b1 - o.W1, o.hW1}, {o.b1, o.W2 - o.b1, -1}, {o.W2, o.b2 - o.W2, o.hW2},
-                 {o.b2, o.W3 - o.b2, -1},     {o.W3, o.b3 - o.W3, o.hW3}, {o.b3, o.total - o.b3, -1}};
+        int32_t k;  // columns of the weight matrix (its BF16 copy is in fragment order)
+    } segs[6] = {{o.W1, o.b1 - o.W1, o.hW1, kIn},     {o.b1, o.W2 - o.b1, -1, 0},
+                 {o.W2, o.b2 - o.W2, o.hW2, kHidden}, {o.b2, o.W3 - o.b2, -1, 0},
+                 {o.W3, o.b3 - o.W3, o.hW3, kHidden}, {o.b3, o.total - o.b3, -1, 0}};
     for (const Seg& sg : segs)
         hipLaunchKernelGGL(adam_kernel, dim3(grid1(sg.n)), dim3(kThreads), 0, st, P + sg.p, grad + sg.p, M1 + sg.p,
-                           M2 + sg.p, sg.n, lr, b1, b2, eps, bc1, bc2, sg.h >= 0 ? Wh + sg.h : nullptr);
+                           M2 + sg.p, sg.n, lr, b1, b2, eps, bc1, bc2, sg.h >= 0 ? Wh + sg.h : nullptr,
+                           sg.k > 0 ? sg.k : 1);
     QS_HIP(hipGetLastError());
     if (loss_out) QS_HIP(hipMemcpyAsync(loss_out, W + w.loss, 4, hipMemcpyDeviceToDevice, st));
     m->meta_host[0] = m->step;

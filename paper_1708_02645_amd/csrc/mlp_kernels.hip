@@ -188,7 +188,7 @@ __global__ void splitk_reduce_kernel(const float* part, int splits, int64_t coun
 }
 
 __global__ void adam_kernel(float* P, const float* Gr, float* M1, float* M2, int64_t n, float lr, float b1, float b2,
-                            float eps, float bc1, float bc2, __bf16* Wh)
+                            float eps, float bc1, float bc2, __bf16* Wh, int32_t frag_k)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -199,13 +199,13 @@ __global__ void adam_kernel(float* P, const float* Gr, float* M1, float* M2, int
     M2[i] = v;
     const float p = P[i] - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
     P[i] = p;
-    if (Wh) Wh[i] = (__bf16)p;
+    if (Wh) Wh[frag_index(i, frag_k)] = (__bf16)p;
 }
 
-__global__ void bf16_copy_kernel(const float* P, __bf16* Wh, int64_t n)
+__global__ void bf16_copy_kernel(const float* P, __bf16* Wh, int64_t n, int32_t frag_k)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) Wh[i] = (__bf16)P[i];
+    if (i < n) Wh[frag_index(i, frag_k)] = (__bf16)P[i];
 }
 
 // Per-orbital statistics of a target batch: sums of V, V^2, G, G^2 (three

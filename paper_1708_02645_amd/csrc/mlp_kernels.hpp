@@ -45,12 +45,29 @@ __host__ __device__ inline MlpOffsets mlp_offsets(int nout)
     return o;
 }
 
+// Position of element i of a row-major [M][K] weight matrix (M a multiple
+// of 16, K of 32) in its BF16 copy, which is kept in matrix-core fragment
+// order: fragment (b, t) -- rows 16b..16b+15, columns 32t..32t+31 -- is 512
+// consecutive values, b-major, in which lane 16g+c of a wave finds its A
+// operand (row 16b+c, columns 32t+8g..+7) as 8 consecutive values, so one
+// wave loads a fragment as one contiguous 1 KB block.
+__host__ __device__ inline int64_t frag_index(int64_t i, int K)
+{
+    const int64_t r = i / K;
+    const int k = (int)(i - r * K);
+    const int64_t blk = r >> 4;
+    const int c = (int)(r & 15), t = k >> 5, g = (k >> 3) & 3, j = k & 7;
+    return (blk * (K >> 5) + t) * 512 + (16 * g + c) * 8 + j;
+}
+
 struct MlpFwdArgs {
     const double* pos;    // [B][3]
     int64_t B;
     const int32_t* freqs;  // [kFreq][3]
     double cell[3];
-    const __bf16* Wh;      // BF16 weights (hW1, hW2, hW3 offsets)
+    double icell[3];       // 1 / cell
+    double tpc[3];         // 2 pi / cell
+    const __bf16* Wh;      // BF16 weights in fragment order (hW1, hW2, hW3 offsets)
     const float* P;        // FP32 parameters (biases)
     const float* mu;       // [nout]
     const float* sd;       // [nout]
