@@ -243,7 +243,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 forms")
     ap.add_argument("--no-ragged", action="store_true", help="skip the four-table ragged plan")
-    ap.add_argument("--mlp-steps", type=int, default=6000, help="training steps of the surrogate (0 skips it)")
+    ap.add_argument("--mlp-steps", type=int, default=24000, help="training steps of the surrogate (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle wall time")
     ap.add_argument("--tile", type=str, default="", help="cw,nch,lpp,pb (skips the autotuner)")

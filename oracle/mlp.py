@@ -32,6 +32,12 @@ and L, each error taken relative to that orbital's largest |quantity| over the
 whole validation set; positions in bins whose error exceeds a tolerance are
 routed to the spline.
 
+The representational floor: bandlimited_vgl evaluates the spline's Fourier
+series cut to the feature frequencies' ball (from the definition of the
+spline and the transform of the cubic B-spline); the error of that against
+the spline is the least any approximant whose spectrum stays below the
+table's first alias band can reach.
+
 Parity status: every function here is pinned by tests/test_oracle_mlp.py
 (closed forms, finite differences, hand-built cases and scalar loops).  The
 network's accuracy as a surrogate of a spline table has no reference value:
@@ -262,3 +268,46 @@ def route(pos, bin_err, bins_per_dim, tol, cell=(1.0, 1.0, 1.0)):
     with np.errstate(invalid="ignore"):
         keep = e <= t
     return np.flatnonzero(~keep).astype(np.int64)
+
+
+def spline_fourier_coefficients(coefs, kmax, cell=(1.0, 1.0, 1.0)):
+    """Fourier coefficients of the periodic tricubic spline at the integer
+    frequencies k with |k|_2 <= kmax (each below half the grid on every axis).
+
+    The spline is s(r) = sum_j c_j prod_d beta(n_d r_d / cell_d - j_d), beta
+    the centred cubic B-spline, whose Fourier transform is sinc(x)^4 (sinc(x)
+    = sin(pi x) / (pi x)).  Its Fourier series coefficient at k is therefore
+    chat(k) prod_d sinc(k_d / n_d)^4, with chat(k) = (1/|n|) sum_j c_j
+    exp(-2 pi i k.j / n) the discrete transform of the coefficients.  Returns
+    (K[m,3] int64, S[m,N] complex128)."""
+    c = np.asarray(coefs, dtype=np.float64)
+    n = np.array(c.shape[:3])
+    N = c.shape[3]
+    r = int(np.floor(kmax))
+    ax = np.arange(-r, r + 1)
+    K = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    K = K[(K ** 2).sum(1) <= kmax * kmax + 1e-9]
+    if np.any(2 * np.abs(K) >= n[None, :]):
+        raise ValueError("kmax must stay below half the grid on every axis")
+    chat = np.fft.fftn(c, axes=(0, 1, 2)) / float(np.prod(n))
+    Cs = chat[K[:, 0] % n[0], K[:, 1] % n[1], K[:, 2] % n[2]].reshape(-1, N)
+    damp = np.prod(np.sinc(K / n[None, :]) ** 4, axis=1)
+    return K, Cs * damp[:, None]
+
+
+def bandlimited_vgl(coefs, pos, kmax, cell=(1.0, 1.0, 1.0)):
+    """V[B,N], G[B,3,N], L[B,N] of the spline's Fourier series truncated to
+    |k| <= kmax: the L2-closest function over the cell whose spectrum lies in
+    that ball.  For a table fitted to plane waves with |G| <= kmax, every
+    other component of the spline sits at an alias k + n a (a != 0), so this
+    is the best any approximant reaching only frequencies below the first
+    alias band can do (the surrogate's features are such frequencies)."""
+    K, S = spline_fourier_coefficients(coefs, kmax, cell)
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    cell = np.asarray(cell, dtype=np.float64)
+    kc = TWO_PI * K / cell[None, :]                        # [m,3] Cartesian wave vectors
+    ph = np.exp(1j * (pos / cell[None, :] * TWO_PI) @ K.T)  # [B,m]
+    V = (ph @ S).real
+    G = np.stack([((1j * kc[:, d])[None, :] * ph) @ S for d in range(3)], 1).real
+    L = ((-(kc ** 2).sum(1))[None, :] * ph @ S).real
+    return V, G, L
