@@ -242,9 +242,14 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
  *             for the quadrature points of the non-local pseudopotential.
  * Outputs float (double for SPL_F64); per-position sums are added in a fixed
  * order, so results are reproducible bit for bit for a given tile shape.
- * The handle's VGL (value) tile shape is used.  Asynchronous on `stream`;
- * B == 0 is a no-op.  SPL_EINVAL on NULL pointers, ld < 0 or misaligned
- * rows; SPL_EUNSUPPORTED when no ratio kernel exists for the tile shape. */
+ * The handle's VGL (value) tile shape is used.  For a table with a general
+ * cell (spline_set_lattice) the ratio with derivatives is formed by the
+ * VGH-family kernel (the handle's VGH tile shape; Cartesian G and L from the
+ * full Hessian) and the locality-ordered form uses the locality-ordered VGH
+ * shape; the value ratio needs no derivatives and is the same kernel in any
+ * cell.  Asynchronous on `stream`; B == 0 is a no-op.  SPL_EINVAL on NULL
+ * pointers, ld < 0 or misaligned rows; SPL_EUNSUPPORTED when no ratio kernel
+ * exists for the tile shape. */
 int spline_eval_ratio_vgl(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
                           int64_t ld, const int32_t* rows_dev, void* D, void* stream);
 int spline_eval_ratio_v(const spline_t* s, const double* pos_dev, int64_t B, const void* ainv_dev,
@@ -336,10 +341,11 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv_dev, int64_t walker_stride, vo
  * graphite cell is hexagonal, for example.  SPL_EINVAL if the matrix is not
  * finite or is singular.  Host only; the table is not touched.  Afterwards
  * spline_eval_vgh, spline_eval_vgl (a general-cell kernel that forms the
- * Laplacian from the full Hessian), spline_eval_v, spline_eval_ratio_v and
- * spline_autotune (which then tunes the general-cell kernels) serve the
- * cell; spline_eval_ratio_vgl, plans and the surrogate's spline fallback
- * return SPL_EUNSUPPORTED for such a table.
+ * Laplacian from the full Hessian), spline_eval_v, spline_eval_ratio_v,
+ * spline_eval_ratio_vgl, their locality-ordered forms and spline_autotune
+ * (which then tunes the general-cell kernels) serve the cell; plans and the
+ * surrogate's spline fallback return SPL_EUNSUPPORTED for such a table (the
+ * surrogate's features are periodic in an orthorhombic cell).
  * spline_get_lattice returns it (diag(cell) for an orthorhombic table). */
 int spline_set_lattice(spline_t* s, const double* lattice);
 int spline_get_lattice(const spline_t* s, double* lattice);

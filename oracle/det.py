@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import eval_v, eval_vgl
+from . import eval_v, eval_vgh, eval_vgl
 
 
 def slater_matrix(grid, coefs: np.ndarray, R: np.ndarray, cell=(1.0, 1.0, 1.0)) -> np.ndarray:
@@ -41,6 +41,22 @@ def ratio_vgl(grid, coefs: np.ndarray, pos: np.ndarray, rows: np.ndarray, cell=(
     """D[B, 5]: for position b and its row a = rows[b] (length N, the table's
     orbital count), (sum a V, sum a Gx, sum a Gy, sum a Gz, sum a L)."""
     V, G, L = eval_vgl(grid, coefs, pos, cell)
+    a = np.asarray(rows, dtype=np.float64).reshape(V.shape)
+    D = np.empty((V.shape[0], 5))
+    D[:, 0] = np.sum(a * V, axis=1)
+    for d in range(3):
+        D[:, 1 + d] = np.sum(a * G[:, d, :], axis=1)
+    D[:, 4] = np.sum(a * L, axis=1)
+    return D
+
+
+def ratio_vgl_lattice(grid, coefs: np.ndarray, pos: np.ndarray, rows: np.ndarray, lattice) -> np.ndarray:
+    """ratio_vgl in a general cell (rows of `lattice` are the Cartesian
+    lattice vectors): the orbital values, Cartesian gradients and Laplacians
+    (the trace of the Cartesian Hessian) from the general-cell oracle, each
+    dotted with the position's row."""
+    V, G, H = eval_vgh(grid, coefs, pos, lattice)
+    L = H[:, 0] + H[:, 3] + H[:, 5]  # xx + yy + zz
     a = np.asarray(rows, dtype=np.float64).reshape(V.shape)
     D = np.empty((V.shape[0], 5))
     D[:, 0] = np.sum(a * V, axis=1)

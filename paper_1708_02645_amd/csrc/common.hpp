@@ -126,6 +126,13 @@ void set_general_args(const spline_s* s, EvalArgs& a);
 int vgl_general(const spline_s* s, const double* pos, int64_t B, void* V, void* G, void* L, hipStream_t st);
 int vgh_launch_indexed(const spline_s* s, const spline_tile& t, bool hessian, const double* pos, int64_t B, void* V,
                        void* G, void* H, const int32_t* idx, hipStream_t st);
+// Fused determinant ratio with derivatives in a general cell (the VGH-family
+// kernel with the ratio epilogue): ratio_general_tile halves t.pb until the
+// partial sums fit in LDS; ratio_general launches it (idx: optional
+// position order, as in the locality-ordered evaluation).
+int ratio_general_tile(const spline_s* s, spline_tile& t);
+int ratio_general(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, const void* ainv, int64_t ld,
+                  const int32_t* rows, void* D, const int32_t* idx, hipStream_t st);
 // Tile of the locality-ordered VGH family: 16-lane groups with the widest
 // chunk compiled for the storage type where it fits the row (else the VGH
 // tile's shape), at most 8 positions per workgroup.

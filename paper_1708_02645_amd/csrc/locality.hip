@@ -323,11 +323,21 @@ static int sorted_ratio(const spline_s* s, const double* pos, int64_t B, const v
     if (ld < 0) return fail(SPL_EINVAL, "ld must be >= 0");
     int rc = sorted_check(s, pos, B, D, D, D, ws, ws_bytes, false);
     if (rc || B == 0) return rc;
-    if (s->general) return fail(SPL_EUNSUPPORTED, "the fused ratio is built for orthorhombic cells");
     if (!ainv) return fail(SPL_EINVAL, "NULL inverse-row pointer");
     const uintptr_t eb = s->store == SPL_F64 ? 8 : 4;
     if ((uintptr_t)ainv % eb || (uintptr_t)D % eb)
         return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
+    if (s->general && vgl) {
+        // the VGH-family ratio kernel with the locality-ordered VGH shape
+        spline_tile t = vgh_sorted_tile(s);
+        rc = ratio_general_tile(s, t);
+        if (rc) return rc;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int32_t* perm = nullptr;
+        rc = sort_positions(s, pos, B, t.pb, ws, st, &perm);
+        if (rc) return rc;
+        return ratio_general(s, t, pos, B, ainv, ld, rows, D, perm, st);
+    }
     spline_tile t = vgl ? s->stile : s->svtile;
     const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
     if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");

@@ -490,8 +490,16 @@ static int ratio_common(const spline_t* s, const double* pos, int64_t B, const v
         return fail(SPL_EINVAL, "inverse rows and outputs must be aligned to their element size");
     int64_t tmp;
     if (!mul_ok(B, 5 * 8, &tmp)) return fail(SPL_ENOMEM, "output size overflow");
-    if (s->general && vgl)
-        return fail(SPL_EUNSUPPORTED, "ratio with derivatives is built for orthorhombic cells only");
+    if (s->general && vgl) {
+        // the VGH-family kernel with the ratio epilogue (Cartesian G and L)
+        spline_tile t = s->htile;
+        int rc = ratio_general_tile(s, t);
+        if (rc) return rc;
+        int dev = -1;
+        QS_HIP(hipGetDevice(&dev));
+        if (dev != s->device) return fail(SPL_EINVAL, "current HIP device differs from the table's device");
+        return ratio_general(s, t, pos, B, ainv, ld, rows, D, nullptr, static_cast<hipStream_t>(stream));
+    }
     spline_tile t = vgl ? s->tile : s->vtile;
     const Variant* v = find_variant(s->store, t.cw, t.nch, t.lpp, vgl, true);
     if (!v) return fail(SPL_EUNSUPPORTED, "no determinant-ratio kernel for this tile shape");

@@ -156,12 +156,22 @@ static VghArgs make_vgh_args(const spline_s* s, const spline_tile& t, const doub
     return va;
 }
 
+// LDS of a VGH-family launch: the staged weights, and for the ratio the
+// per-(position, tile) partial sums after them.
+static size_t vgh_lds(const spline_s* s, const VghVariant& v, const spline_tile& t)
+{
+    size_t per = v.lds_per_pos;
+    if (v.out == VGH_OUT_RATIO) per += (size_t)tiles_of(s, t) * 5 * (s->store == SPL_F64 ? 8 : 4);
+    return per * (size_t)t.pb;
+}
+
 static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const double* pos, int64_t B, void* V,
-                      void* G, void* H, hipStream_t st, const int32_t* idx = nullptr)
+                      void* G, void* H, hipStream_t st, const int32_t* idx = nullptr, const void* ainv = nullptr,
+                      int64_t ld = 0, const int32_t* rows = nullptr)
 {
     const VghVariant* v = find_vgh(s->store, t, out);
     if (!v || !vgh_fits(s, *v)) return fail(SPL_EUNSUPPORTED, "tile shape not compiled for the VGH kernels");
-    if (t.pb < 1 || v->lds_per_pos * (size_t)t.pb > kMaxLds) return fail(SPL_EUNSUPPORTED, "bad positions per workgroup");
+    if (t.pb < 1 || vgh_lds(s, *v, t) > kMaxLds) return fail(SPL_EUNSUPPORTED, "bad positions per workgroup");
     int dev = -1;
     QS_HIP(hipGetDevice(&dev));
     if (dev != s->device) return fail(SPL_EINVAL, "current HIP device differs from the table's device");
@@ -169,10 +179,28 @@ static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const do
     if (blocks > (int64_t)std::numeric_limits<int32_t>::max()) return fail(SPL_EINVAL, "batch too large for one launch");
     VghArgs va = make_vgh_args(s, t, pos, B, V, G, H);
     va.e.idx = idx;
+    va.e.ainv = ainv;
+    va.e.ald = ld;
+    va.e.arows = rows;
     void* params[] = {&va};
-    QS_HIP(hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(kBlock), params, v->lds_per_pos * (size_t)t.pb, st));
+    QS_HIP(hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(kBlock), params, vgh_lds(s, *v, t), st));
     QS_HIP(hipGetLastError());
     return SPL_OK;
+}
+
+int ratio_general_tile(const spline_s* s, spline_tile& t)
+{
+    const VghVariant* v = find_vgh(s->store, t, VGH_OUT_RATIO);
+    if (!v || !vgh_fits(s, *v)) return fail(SPL_EUNSUPPORTED, "tile shape not compiled for the VGH kernels");
+    while (t.pb > 1 && vgh_lds(s, *v, t) > kMaxLds) t.pb /= 2;
+    if (vgh_lds(s, *v, t) > kMaxLds) return fail(SPL_EUNSUPPORTED, "row too wide for the partial sums");
+    return SPL_OK;
+}
+
+int ratio_general(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, const void* ainv, int64_t ld,
+                  const int32_t* rows, void* D, const int32_t* idx, hipStream_t st)
+{
+    return vgh_launch(s, t, VGH_OUT_RATIO, pos, B, D, nullptr, nullptr, st, idx, ainv, ld, rows);
 }
 
 // General-cell VGL (used by spline_eval_vgl for a handle with a lattice).

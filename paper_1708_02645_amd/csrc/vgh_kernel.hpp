@@ -15,14 +15,18 @@
 //   H_h = sum_k P[h][k] h_k                 (P: the 6x6 map of M (.) M^T on
 //                                            symmetric matrices)
 //   L   = sum_k K[k] h_k                    (K: the trace of that map)
-// OUT selects the stores: VGH (V, G, H[6]) or general-cell VGL (V, G, L).
+// OUT selects the stores: VGH (V, G, H[6]), general-cell VGL (V, G, L), or
+// the fused determinant ratio with derivatives (RATIO: the Cartesian V, G, L
+// dotted with the position's row of A^-1, five numbers per position, summed
+// as in eval_block: lanes by a butterfly, tiles in tile order after a
+// barrier).
 #pragma once
 
 #include "eval_kernel.hpp"
 
 namespace qs {
 
-enum { VGH_OUT_H = 0, VGH_OUT_L = 1 };
+enum { VGH_OUT_H = 0, VGH_OUT_L = 1, VGH_OUT_RATIO = 2 };
 
 struct VghArgs {
     EvalArgs e;         // e.V, e.G as usual; e.general = 1; e.L unused for OUT_H
@@ -63,6 +67,11 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
     const int lane = tid % LPP;
     const int items = np * a.tiles;
     const uint32_t loff = (uint32_t)lane * CHB;
+    // RATIO: per-(position, tile) sums in LDS after the staged weights.
+    TA* part = reinterpret_cast<TA*>(W + a.pb);
+    bool row_aligned = false;
+    if constexpr (OUT == VGH_OUT_RATIO)
+        row_aligned = a.ald % VPC == 0 && (uintptr_t)a.ainv % alignof(Pack<TA, VPC>) == 0;
 
     for (int it = g; it < items; it += groups) {
         const int item = (LPP == 64) ? uniform<int>(it) : it;
@@ -225,10 +234,14 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
         TA* Vo = reinterpret_cast<TA*>(a.V) + b * a.norb;
         TA* Go = reinterpret_cast<TA*>(a.G) + (3 * b) * a.norb;
         TA* Ho = reinterpret_cast<TA*>(va.H) + (OUT == VGH_OUT_H ? 6 : 1) * b * a.norb;
+        [[maybe_unused]] TA rsum[5] = {TA(0), TA(0), TA(0), TA(0), TA(0)};
+        [[maybe_unused]] const TA* ar = nullptr;
+        if constexpr (OUT == VGH_OUT_RATIO)
+            ar = reinterpret_cast<const TA*>(a.ainv) + (a.arows ? (int64_t)a.arows[b] : b) * a.ald;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int o = tile * TO + c * LPP * VPC + lane * VPC;
-            if (o >= a.norb) continue;
+            if (OUT != VGH_OUT_RATIO && o >= a.norb) continue;
             TA sc[VPC];
 #pragma unroll
             for (int i = 0; i < VPC; ++i) {
@@ -264,12 +277,51 @@ __device__ inline void vgh_block(const VghArgs& va, int64_t b0, int np, PosW<typ
                     oh[0][i] = acc;
                 }
             }
+            if constexpr (OUT == VGH_OUT_RATIO) {
+                // padding orbitals (o >= norb) hold zero coefficients and get
+                // zero inverse-row entries
+                TA av[VPC];
+                load_vals<TA, VPC>(ar, av, o, a.norb, row_aligned);
+#pragma unroll
+                for (int i = 0; i < VPC; ++i) {
+                    rsum[0] = fma(av[i], ov[i], rsum[0]);
+                    rsum[1] = fma(av[i], og[0][i], rsum[1]);
+                    rsum[2] = fma(av[i], og[1][i], rsum[2]);
+                    rsum[3] = fma(av[i], og[2][i], rsum[3]);
+                    rsum[4] = fma(av[i], oh[0][i], rsum[4]);
+                }
+                continue;
+            }
             store_vals<TA, VPC>(Vo, ov, o, a.norb, aligned);
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) store_vals<TA, VPC>(Go + cc * a.norb, og[cc], o, a.norb, aligned);
 #pragma unroll
             for (int h = 0; h < (OUT == VGH_OUT_H ? 6 : 1); ++h)
                 store_vals<TA, VPC>(Ho + h * a.norb, oh[h], o, a.norb, aligned);
+        }
+        if constexpr (OUT == VGH_OUT_RATIO) {
+#pragma unroll
+            for (int m = LPP / 2; m >= 1; m >>= 1)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) rsum[q] += __shfl_xor(rsum[q], m, LPP);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) part[(p * a.tiles + tile) * 5 + q] = rsum[q];
+            }
+        }
+    }
+    if constexpr (OUT == VGH_OUT_RATIO) {
+        __syncthreads();
+        for (int p = tid; p < np; p += kBlock) {
+            TA sum[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sum[q] = part[p * a.tiles * 5 + q];
+            for (int t = 1; t < a.tiles; ++t)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sum[q] += part[(p * a.tiles + t) * 5 + q];
+            TA* D = reinterpret_cast<TA*>(a.V) + W[p].row * 5;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) D[q] = sum[q];
         }
     }
 }
@@ -315,7 +367,9 @@ struct VghVariant {
     {ST, CW, NCH, LPP, VGH_OUT_H, (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_H>,   \
      sizeof(PosW<Acc<ST>::type>)},                                                         \
     {ST, CW, NCH, LPP, VGH_OUT_L, (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_L>,   \
-     sizeof(PosW<Acc<ST>::type>)},
+     sizeof(PosW<Acc<ST>::type>)},                                                         \
+    {ST, CW, NCH, LPP, VGH_OUT_RATIO,                                                      \
+     (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_RATIO>, sizeof(PosW<Acc<ST>::type>)},
 
 #define QS_VGH_REGISTRY(NAME, LIST, ST)                                                   \
     static const VghVariant k_vgh_variants[] = {LIST(QS_VGH_VARIANTS, ST)};               \

@@ -93,7 +93,7 @@ def test_edges(torch, q):
         _say("case sorted grid", g_small)
         _check_equal(torch, s1, rng.uniform(-3, 3, (257, 3)))
         s1.close()
-    # B == 0 is a no-op; a short workspace and a general cell are refused
+    # B == 0 is a no-op; a short workspace is refused, and the value-only form refuses a general cell
     e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
     s.eval_vgl_sorted(e)
     pos = torch.from_numpy(rng.random((64, 3))).cuda()
@@ -106,8 +106,9 @@ def test_edges(torch, q):
     s.set_lattice([[1.3, 0, 0], [0.2, 0.7, 0], [0, 0, 2.1]])
     with pytest.raises(q.SplineError):
         s.eval_v_sorted(pos)  # value only: orthorhombic cells
-    with pytest.raises(q.SplineError):
-        s.eval_ratio_vgl_sorted(pos, torch.zeros((64, 40), dtype=torch.float32, device="cuda"))
+    # the ratio with derivatives serves general cells (parity in test_gpu_vgh)
+    D = s.eval_ratio_vgl_sorted(pos, torch.zeros((64, 40), dtype=torch.float32, device="cuda"))
+    assert tuple(D.shape) == (64, 5) and bool((D == 0).all())
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])

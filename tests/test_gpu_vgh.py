@@ -192,10 +192,10 @@ def test_edges_and_unsupported(torch, q, oracle):
     assert np.all(np.isfinite(V[ok])) and np.all(np.isfinite(H[ok]))
     e = s.eval_vgh(pd[:0])
     assert tuple(e[2].shape) == (0, 6, N)
-    rows = torch.zeros((65, N), dtype=torch.float32, device="cuda")
-    with pytest.raises(q.SplineError) as ex:
-        s.eval_ratio_vgl(pd, rows)
-    assert ex.value.code == -4
+    # the ratio with derivatives: NaN for the non-finite position only
+    rows = torch.ones((65, N), dtype=torch.float32, device="cuda")
+    D = s.eval_ratio_vgl(pd, rows).cpu().numpy()
+    assert np.all(np.isnan(D[10])) and np.all(np.isfinite(D[ok]))
     # value-only ratio serves general cells
     rows = torch.from_numpy(np.random.default_rng(1).normal(size=(65, N)).astype(np.float32)).cuda()
     R = s.eval_ratio_v(pd, rows).cpu().numpy()
@@ -209,3 +209,46 @@ def test_edges_and_unsupported(torch, q, oracle):
     with pytest.raises(q.SplineError) as ex:
         q.Plan([s], [pd])
     assert ex.value.code == -4
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("name", ["hexagonal", "triclinic"])
+def test_general_ratio_with_derivatives(torch, q, oracle, dtype, name):
+    """Fused determinant ratio with derivatives in a general cell (the
+    VGH-family kernel with the ratio epilogue), plain and locality-ordered,
+    against the oracle's dot products of each row with V, the Cartesian G
+    and the trace of the Cartesian Hessian.  Error measure of the ratio
+    tests: |D - D_ref| / sum_i |a_i| max|Q_i|; same bars as VGL."""
+    from oracle import det
+
+    lat = LATTICES[name]
+    grid, N, coefs, _ = W.make_table(1)
+    rng = np.random.default_rng(41)
+    pos = _positions(rng, 777, lat)
+    _say("case general ratio", dtype, name)
+    s = q.Spline(grid, coefs, dtype)
+    s.set_lattice(lat)
+    table = _ref_coefs(oracle, coefs, dtype)
+    fdt = np.float64 if dtype == "f64" else np.float32
+    # rows through an index map with a stride of 2N (quadrature points
+    # sharing an electron's row)
+    ainv = rng.standard_normal((400, 2 * N)).astype(fdt)
+    idx = rng.integers(0, 400, len(pos)).astype(np.int32)
+    rows64 = ainv[idx, :N].astype(np.float64)
+    Dref = det.ratio_vgl_lattice(grid, table, pos, rows64, lat)
+    V, G, H = oracle.eval_vgh(grid, table, pos, lat)
+    M = [np.abs(V).max(0), np.abs(G).max((0, 1)), np.abs(H[:, 0] + H[:, 3] + H[:, 5]).max(0)]
+    sv, sg, sl = (det.ratio_scale(rows64, m) for m in M)
+    scale = np.stack([sv, sg, sg, sg, sl], 1)
+    pd = torch.from_numpy(pos).cuda()
+    ad = torch.from_numpy(ainv).cuda()
+    rd = torch.from_numpy(idx).cuda()
+    for how in ("plain", "sorted"):
+        if how == "plain":
+            D = s.eval_ratio_vgl(pd, ad, ld=2 * N, rows=rd)
+        else:
+            D = s.eval_ratio_vgl_sorted(pd, ad, ld=2 * N, rows=rd)
+        D = D.double().cpu().numpy()
+        e = float(np.max(np.abs(D - Dref) / scale))
+        _say("  %s eps %.2e" % (how, e))
+        assert e <= TOL[dtype], (how, e)

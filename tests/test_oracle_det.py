@@ -168,3 +168,43 @@ def test_delayed_update_matches_direct_inverses(oracle):
     new = det.delayed_flush(A0inv, phis, ks)
     want = np.linalg.inv(det.slater_matrix(grid, coefs, R2))
     assert np.max(np.abs(new - want)) < 1e-8 * np.max(np.abs(want))
+
+
+def test_general_cell_ratio(oracle):
+    """ratio_vgl_lattice: equal to ratio_vgl for a diagonal lattice;
+    covariant under a rotation of lattice and positions (value and Laplacian
+    invariant, gradient rotated); and its derivatives are central differences
+    of its value in a hexagonal cell."""
+    from oracle import det
+
+    rng = np.random.default_rng(31)
+    grid = (9, 10, 11)
+    N = 7
+    coefs = rng.uniform(-1, 1, grid + (N,))
+    rows = rng.standard_normal((12, N))
+    cell = (1.0, 1.3, 0.8)
+    pos = rng.uniform(0, 1, (12, 3)) * np.array(cell)
+    np.testing.assert_allclose(det.ratio_vgl_lattice(grid, coefs, pos, rows, np.diag(cell)),
+                               det.ratio_vgl(grid, coefs, pos, rows, cell), rtol=1e-11, atol=1e-9)
+    hexl = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3.0) / 2.0, 0.0], [0.0, 0.0, 1.6]])
+    frac = rng.uniform(0.05, 0.95, (12, 3))
+    p = frac @ hexl
+    D = det.ratio_vgl_lattice(grid, coefs, p, rows, hexl)
+    t = 0.7
+    Q = np.array([[np.cos(t), -np.sin(t), 0.0], [np.sin(t), np.cos(t), 0.0], [0.0, 0.0, 1.0]])
+    Dr = det.ratio_vgl_lattice(grid, coefs, p @ Q.T, rows, hexl @ Q.T)
+    np.testing.assert_allclose(Dr[:, 0], D[:, 0], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(Dr[:, 4], D[:, 4], rtol=1e-9, atol=1e-7)
+    np.testing.assert_allclose(Dr[:, 1:4], D[:, 1:4] @ Q.T, rtol=1e-10, atol=1e-9)
+    h1, h2 = 1e-6, 1e-3
+    lap = np.zeros(len(p))
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = 1.0
+        fp = det.ratio_vgl_lattice(grid, coefs, p + h1 * e, rows, hexl)[:, 0]
+        fm = det.ratio_vgl_lattice(grid, coefs, p - h1 * e, rows, hexl)[:, 0]
+        np.testing.assert_allclose((fp - fm) / (2 * h1), D[:, 1 + d], rtol=1e-5, atol=1e-5 * np.abs(D[:, 1:4]).max())
+        gp = det.ratio_vgl_lattice(grid, coefs, p + h2 * e, rows, hexl)[:, 0]
+        gm = det.ratio_vgl_lattice(grid, coefs, p - h2 * e, rows, hexl)[:, 0]
+        lap += (gp - 2 * D[:, 0] + gm) / h2 ** 2
+    np.testing.assert_allclose(lap, D[:, 4], rtol=1e-3, atol=1e-3 * np.abs(D[:, 4]).max())
