@@ -342,10 +342,10 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv_dev, int64_t walker_stride, vo
  * finite or is singular.  Host only; the table is not touched.  Afterwards
  * spline_eval_vgh, spline_eval_vgl (a general-cell kernel that forms the
  * Laplacian from the full Hessian), spline_eval_v, spline_eval_ratio_v,
- * spline_eval_ratio_vgl, their locality-ordered forms and spline_autotune
- * (which then tunes the general-cell kernels) serve the cell; plans and the
- * surrogate's spline fallback return SPL_EUNSUPPORTED for such a table (the
- * surrogate's features are periodic in an orthorhombic cell).
+ * spline_eval_ratio_vgl, their locality-ordered forms, plans and
+ * spline_autotune (which then tunes the general-cell kernels) serve the
+ * cell; the surrogate's spline fallback returns SPL_EUNSUPPORTED for such a
+ * table (the surrogate's features are periodic in an orthorhombic cell).
  * spline_get_lattice returns it (diag(cell) for an orthorhombic table). */
 int spline_set_lattice(spline_t* s, const double* lattice);
 int spline_get_lattice(const spline_t* s, double* lattice);
@@ -404,7 +404,13 @@ int spline_get_value_tile(const spline_t* s, spline_tile* tile);
  * position and output buffers (same shapes and element types as
  * spline_eval_vgl) and to the workspace; their contents may change between
  * launches, their addresses may not.  Concurrent launches of one plan race on
- * its workspace. */
+ * its workspace.  When a table has a general cell (spline_set_lattice) every
+ * task of the plan runs the VGH-family kernel (the Laplacian from the full
+ * Hessian; orthorhombic tables through their diagonal lattice, equal to
+ * spline_eval_vgl within rounding) and the shapes are the VGH family's; a
+ * general table's outputs equal its spline_eval_vgl under the plan's shape
+ * bit for bit.  Otherwise every table's outputs equal its spline_eval_vgl
+ * bit for bit. */
 typedef struct spline_plan_s spline_plan_t;
 
 /* Device workspace bytes a plan over these batch sizes needs (counter, table

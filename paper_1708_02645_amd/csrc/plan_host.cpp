@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "vgh_kernel.hpp"
 
 namespace qs {
 
@@ -45,7 +46,8 @@ static bool ws_layout(int32_t n_tabs, const int64_t* B, bool sorted, WsLayout* w
     }
     w->counter = 0;  // kPlanSegs counters in the first 256 bytes
     w->tabs = 256;
-    w->tasks = w->tabs + align256((size_t)n_tabs * sizeof(EvalArgs));
+    // per-table kernel arguments: EvalArgs, or VghArgs for a plan with a general cell
+    w->tasks = w->tabs + align256((size_t)n_tabs * std::max(sizeof(EvalArgs), sizeof(VghArgs)));
     w->total = w->tasks + align256((size_t)std::max<int64_t>(nt, 1) * sizeof(PlanTask));
     w->loc.clear();
     if (sorted)
@@ -67,7 +69,9 @@ struct spline_plan_s {
     unsigned char* ws = nullptr;
     qs::WsLayout lay{};
     spline_tile tile{};
-    const qs::Variant* var = nullptr;
+    bool vgh = false;                 // a table has a general cell: every task runs the VGH-family kernel
+    const void* fn = nullptr;         // the plan kernel of the chosen shape
+    size_t lds_per_pos = 0;
     int32_t ntasks = 0;
     int64_t max_tasks = 0;            // capacity of the task list in the workspace
     int32_t nblocks = 0;
@@ -96,32 +100,53 @@ static std::vector<PlanTask> make_tasks(const spline_plan_s* p, int pb)
     return tasks;
 }
 
-// Uploads the descriptors and tasks for (variant, tile) and sizes the grid.
-static int stage_config(spline_plan_s* p, const Variant* v, const spline_tile& t, hipStream_t st)
+// A candidate plan kernel: its function, staged weights per position, shape.
+struct PlanCand {
+    const void* fn;
+    size_t lds_per_pos;
+    spline_tile t;
+};
+
+// Uploads the descriptors and tasks for a candidate and sizes the grid.
+static int stage_config(spline_plan_s* p, const PlanCand& c, hipStream_t st)
 {
-    std::vector<EvalArgs> args(p->tabs.size());
-    for (size_t i = 0; i < p->tabs.size(); ++i) {
-        args[i] = make_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
-        if (p->sorted) args[i].idx = p->perm[i];
-    }
+    const spline_tile& t = c.t;
     if (t.pb < min_pb(p->sorted)) return fail(SPL_EINVAL, "positions per task below the plan's minimum");
     std::vector<PlanTask> tasks = make_tasks(p, t.pb);
     if ((int64_t)tasks.size() > p->max_tasks) return fail(SPL_EINVAL, "task list larger than its workspace region");
-    QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(EvalArgs),
-                          hipMemcpyHostToDevice, st));
+    if (p->vgh) {
+        std::vector<VghArgs> args(p->tabs.size());
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            args[i] = vgh_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
+            if (p->sorted) args[i].e.idx = p->perm[i];
+        }
+        QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(VghArgs),
+                              hipMemcpyHostToDevice, st));
+        QS_HIP(hipStreamSynchronize(st));  // the host vector dies at the end of this block
+    } else {
+        std::vector<EvalArgs> args(p->tabs.size());
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            args[i] = make_args(p->tabs[i], t, p->pos[i], p->B[i], p->V[i], p->G[i], p->L[i]);
+            if (p->sorted) args[i].idx = p->perm[i];
+        }
+        QS_HIP(hipMemcpyAsync(p->ws + p->lay.tabs, args.data(), args.size() * sizeof(EvalArgs),
+                              hipMemcpyHostToDevice, st));
+        QS_HIP(hipStreamSynchronize(st));
+    }
     if (!tasks.empty())
         QS_HIP(hipMemcpyAsync(p->ws + p->lay.tasks, tasks.data(), tasks.size() * sizeof(PlanTask),
                               hipMemcpyHostToDevice, st));
     QS_HIP(hipStreamSynchronize(st));  // the host vectors die at return
-    const size_t lds = v->lds_per_pos * (size_t)t.pb;
+    const size_t lds = c.lds_per_pos * (size_t)t.pb;
     int per_cu = 0;
-    QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->plan_fn, kBlock, lds));
+    QS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.fn, kBlock, lds));
     hipDeviceProp_t prop;
     QS_HIP(hipGetDeviceProperties(&prop, p->device));
     const int64_t full = (int64_t)std::max(per_cu, 1) * prop.multiProcessorCount;
     p->ntasks = (int32_t)tasks.size();
     p->nblocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(full, p->ntasks));
-    p->var = v;
+    p->fn = c.fn;
+    p->lds_per_pos = c.lds_per_pos;
     p->tile = t;
     return SPL_OK;
 }
@@ -142,9 +167,12 @@ static int launch_plan(const spline_plan_s* p, hipStream_t st)
     PlanArgs pa{reinterpret_cast<const EvalArgs*>(p->ws + p->lay.tabs),
                 reinterpret_cast<const PlanTask*>(p->ws + p->lay.tasks), counter, p->ntasks,
                 p->sorted ? kPlanSegs : 1};
-    void* params[] = {&pa};
-    const size_t lds = p->var->lds_per_pos * (size_t)p->tile.pb;
-    QS_HIP(hipLaunchKernel(p->var->plan_fn, dim3(p->nblocks), dim3(kBlock), params, lds, st));
+    PlanVghArgs pv{reinterpret_cast<const VghArgs*>(p->ws + p->lay.tabs),
+                   reinterpret_cast<const PlanTask*>(p->ws + p->lay.tasks), counter, p->ntasks,
+                   p->sorted ? kPlanSegs : 1};
+    void* params[] = {p->vgh ? static_cast<void*>(&pv) : static_cast<void*>(&pa)};
+    const size_t lds = p->lds_per_pos * (size_t)p->tile.pb;
+    QS_HIP(hipLaunchKernel(p->fn, dim3(p->nblocks), dim3(kBlock), params, lds, st));
     QS_HIP(hipGetLastError());
     return SPL_OK;
 }
@@ -214,7 +242,6 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
     for (int32_t t = 0; t < n_tabs; ++t) {
         if (!tabs[t]) return fail(SPL_EINVAL, "NULL table handle");
         if (tabs[t]->store != tabs[0]->store) return fail(SPL_EUNSUPPORTED, "tables of one plan must share the storage type");
-        if (tabs[t]->general) return fail(SPL_EUNSUPPORTED, "plans are built for orthorhombic cells only");
         if (tabs[t]->device != dev) return fail(SPL_EINVAL, "table lives on another device");
         if (B_per_tab[t] > 0 && (!pos_dev[t] || !V[t] || !G[t] || !L[t]))
             return fail(SPL_EINVAL, "NULL position or output pointer");
@@ -239,39 +266,53 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
             p->perm.push_back(loc_perm(p->ws + lay.loc[t], B_per_tab[t]));
     hipStream_t st = static_cast<hipStream_t>(stream);
 
+    // A table with a general cell puts the whole plan on the VGH-family
+    // kernel (the others take its general staging with their diagonal
+    // lattice: the same results within rounding).
+    for (int32_t t = 0; t < n_tabs; ++t) p->vgh = p->vgh || tabs[t]->general;
+
     // Candidate shapes: tiles that divide every table's row, times pb.
-    std::vector<std::pair<const Variant*, spline_tile>> cands;
-    int nv = 0;
-    const Variant* vs = variants(&nv);
-    for (int i = 0; i < nv; ++i) {
-        const Variant& v = vs[i];
-        if (!v.vgl || !v.plan_fn || v.store != tabs[0]->store) continue;
-        bool ok = true;
-        for (int32_t t = 0; t < n_tabs && ok; ++t) ok = tile_fits(tabs[t], v);
-        if (!ok) continue;
+    std::vector<PlanCand> cands;
+    auto add = [&](const void* fn, size_t lds_per_pos, int cw, int nch, int lpp) {
         for (int pb : {8, 16, 32, 64}) {
             if (pb == 8 && !sorted) continue;  // short tasks pay only when neighbours share rows
-            if (v.lds_per_pos * (size_t)pb > 64 * 1024) continue;
-            cands.push_back({&v, spline_tile{v.cw, v.nch, v.lpp, pb}});
+            if (lds_per_pos * (size_t)pb > 64 * 1024) continue;
+            cands.push_back(PlanCand{fn, lds_per_pos, spline_tile{cw, nch, lpp, pb}});
+        }
+    };
+    if (p->vgh) {
+        for (const VghVariant* v : vgh_plan_variants(tabs[0]->store)) {
+            bool ok = true;
+            for (int32_t t = 0; t < n_tabs && ok; ++t) ok = vgh_variant_fits(tabs[t], *v);
+            if (ok) add(v->plan_fn, v->lds_per_pos, v->cw, v->nch, v->lpp);
+        }
+    } else {
+        int nv = 0;
+        const Variant* vs = variants(&nv);
+        for (int i = 0; i < nv; ++i) {
+            const Variant& v = vs[i];
+            if (!v.vgl || !v.plan_fn || v.store != tabs[0]->store) continue;
+            bool ok = true;
+            for (int32_t t = 0; t < n_tabs && ok; ++t) ok = tile_fits(tabs[t], v);
+            if (ok) add(v.plan_fn, v.lds_per_pos, v.cw, v.nch, v.lpp);
         }
     }
     if (cands.empty()) {
         delete p;
         return fail(SPL_EUNSUPPORTED, "no compiled tile shape divides every table's row");
     }
-    // Without tuning: the first table's own default shape if it fits all, else
-    // the widest-chunk candidate with positions-per-task 32.
+    // Without tuning: the first table's own default shape (its VGH-family
+    // shape for a plan with a general cell) if it fits all, else the
+    // widest-chunk candidate with positions-per-task 32.
     size_t pick = 0;
     for (size_t i = 0; i < cands.size(); ++i) {
-        const spline_tile& d = tabs[0]->tile;
-        if (cands[i].second.cw == d.cw && cands[i].second.nch == d.nch && cands[i].second.lpp == d.lpp &&
-            cands[i].second.pb == 32) {
+        const spline_tile& d = p->vgh ? tabs[0]->htile : tabs[0]->tile;
+        const spline_tile& c = cands[i].t;
+        if (c.cw == d.cw && c.nch == d.nch && c.lpp == d.lpp && c.pb == 32) {
             pick = i;
             break;
         }
-        if (cands[i].second.pb == 32 && cands[i].second.cw * cands[i].second.nch >
-                                            cands[pick].second.cw * cands[pick].second.nch)
-            pick = i;
+        if (c.pb == 32 && c.cw * c.nch > cands[pick].t.cw * cands[pick].t.nch) pick = i;
     }
     int rc = SPL_OK;
     if (tune_reps > 0 && max_tasks > 0) {
@@ -284,14 +325,14 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
         std::vector<unsigned char> ref, cur;
         float best = 1e30f;
         for (size_t i = 0; i < cands.size() && rc == SPL_OK; ++i) {
-            rc = stage_config(p, cands[i].first, cands[i].second, st);
+            rc = stage_config(p, cands[i], st);
             if (!rc) rc = launch_plan(p, st);
             if (!rc) rc = sample_outputs(p, i == 0 ? ref : cur, st);
             if (rc) break;
             if (i > 0 && cur != ref) {
                 std::ostringstream m;
-                m << "plan autotune: tile (" << cands[i].second.cw << "," << cands[i].second.nch << ","
-                  << cands[i].second.lpp << "," << cands[i].second.pb << ") differs bitwise from the first";
+                m << "plan autotune: tile (" << cands[i].t.cw << "," << cands[i].t.nch << "," << cands[i].t.lpp
+                  << "," << cands[i].t.pb << ") differs bitwise from the first";
                 rc = fail(SPL_EUNSUPPORTED, m.str());
                 break;
             }
@@ -309,7 +350,7 @@ static int plan_create(const spline_t* const* tabs, int32_t n_tabs, const int64_
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
-    if (!rc) rc = stage_config(p, cands[pick].first, cands[pick].second, st);
+    if (!rc) rc = stage_config(p, cands[pick], st);
     if (rc) {
         delete p;
         return rc;

@@ -46,6 +46,16 @@ static bool vgh_fits(const spline_s* s, const VghVariant& v)
     return v.store == s->store && s->layout.row_bytes % tb == 0;
 }
 
+bool vgh_variant_fits(const spline_s* s, const VghVariant& v) { return vgh_fits(s, v); }
+
+std::vector<const VghVariant*> vgh_plan_variants(spline_dtype store)
+{
+    std::vector<const VghVariant*> r;
+    for (const VghVariant& v : vgh_all())
+        if (v.store == store && v.out == VGH_OUT_L && v.plan_fn) r.push_back(&v);
+    return r;
+}
+
 // Candidate VGH-family shapes for this table (OUT_H entries stand for both).
 static std::vector<spline_tile> vgh_candidates(const spline_s* s)
 {
@@ -163,6 +173,11 @@ static size_t vgh_lds(const spline_s* s, const VghVariant& v, const spline_tile&
     size_t per = v.lds_per_pos;
     if (v.out == VGH_OUT_RATIO) per += (size_t)tiles_of(s, t) * 5 * (s->store == SPL_F64 ? 8 : 4);
     return per * (size_t)t.pb;
+}
+
+VghArgs vgh_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G, void* H)
+{
+    return make_vgh_args(s, t, pos, B, V, G, H);
 }
 
 static int vgh_launch(const spline_s* s, const spline_tile& t, int out, const double* pos, int64_t B, void* V,

@@ -22,6 +22,8 @@
 // barrier).
 #pragma once
 
+#include <vector>
+
 #include "eval_kernel.hpp"
 
 namespace qs {
@@ -339,13 +341,58 @@ __global__ __launch_bounds__(kBlock) void vgh_kernel(VghArgs va)
     vgh_block<S, CW, NCH, LPP, OUT>(va, b0, np, W);
 }
 
-// Registry entry of one compiled VGH-family kernel.
+// Several tables in one launch through the VGH-family kernel (the
+// general-cell VGL, V, G and the trace of the Cartesian Hessian): the
+// persistent work queue of plan_kernel (eval_kernel.hpp), each task running
+// vgh_block on its table's arguments.
+struct PlanVghArgs {
+    const VghArgs* tabs;    // device, one per table
+    const PlanTask* tasks;  // device, ntasks entries
+    unsigned int* counter;  // device work counters (one per segment), zero at launch
+    int32_t ntasks;
+    int32_t nseg;
+};
+
+template <spline_dtype S, int CW, int NCH, int LPP>
+__global__ __launch_bounds__(kBlock) void plan_vgh_kernel(PlanVghArgs pa)
+{
+    using TA = typename Acc<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    PosW<TA>* W = reinterpret_cast<PosW<TA>*>(lds_raw);
+    __shared__ int s_task;
+    const int home = (int)(blockIdx.x % (unsigned)pa.nseg);
+    for (int k = 0; k < pa.nseg; ++k) {
+        const int seg = (home + k) % pa.nseg;
+        const int t0 = (int)((int64_t)pa.ntasks * seg / pa.nseg);
+        const int t1 = (int)((int64_t)pa.ntasks * (seg + 1) / pa.nseg);
+        for (;;) {
+            if (threadIdx.x == 0) s_task = t0 + (int)atomicAdd(pa.counter + seg, 1u);
+            __syncthreads();
+            const int t = uniform<int>(s_task);
+            __syncthreads();  // every thread has read s_task before it can be rewritten
+            if (t >= t1) break;  // uniform across the workgroup
+            const PlanTask tk = pa.tasks[t];
+            vgh_block<S, CW, NCH, LPP, VGH_OUT_L>(pa.tabs[tk.table], tk.first, tk.count, W);
+            __syncthreads();  // W is rewritten by the next task
+        }
+    }
+}
+
+// Registry entry of one compiled VGH-family kernel (plan_fn: the plan
+// kernel of the shape, on the general-cell VGL entry).
 struct VghVariant {
     spline_dtype store;
     int cw, nch, lpp, out;
     const void* fn;
     size_t lds_per_pos;
+    const void* plan_fn;
 };
+
+// Host side (vgh_host.cpp): the kernel arguments of a VGH-family launch, and
+// the compiled general-cell VGL variants (for plans).
+VghArgs vgh_args(const spline_s* s, const spline_tile& t, const double* pos, int64_t B, void* V, void* G, void* H);
+std::vector<const VghVariant*> vgh_plan_variants(spline_dtype store);
+bool vgh_variant_fits(const spline_s* s, const VghVariant& v);
 
 }  // namespace qs
 
@@ -365,11 +412,11 @@ struct VghVariant {
 
 #define QS_VGH_VARIANTS(ST, CW, NCH, LPP)                                                 \
     {ST, CW, NCH, LPP, VGH_OUT_H, (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_H>,   \
-     sizeof(PosW<Acc<ST>::type>)},                                                         \
+     sizeof(PosW<Acc<ST>::type>), nullptr},                                                \
     {ST, CW, NCH, LPP, VGH_OUT_L, (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_L>,   \
-     sizeof(PosW<Acc<ST>::type>)},                                                         \
+     sizeof(PosW<Acc<ST>::type>), (const void*)&plan_vgh_kernel<ST, CW, NCH, LPP>},        \
     {ST, CW, NCH, LPP, VGH_OUT_RATIO,                                                      \
-     (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_RATIO>, sizeof(PosW<Acc<ST>::type>)},
+     (const void*)&vgh_kernel<ST, CW, NCH, LPP, VGH_OUT_RATIO>, sizeof(PosW<Acc<ST>::type>), nullptr},
 
 #define QS_VGH_REGISTRY(NAME, LIST, ST)                                                   \
     static const VghVariant k_vgh_variants[] = {LIST(QS_VGH_VARIANTS, ST)};               \

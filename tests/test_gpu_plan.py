@@ -183,3 +183,59 @@ def test_c4_ragged_workload(torch, q, oracle):
     for o, e in zip(outs_s, plain):
         for a, b in zip(o, e):
             assert torch.equal(a, b)
+
+
+HEX = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3.0) / 2.0, 0.0], [0.0, 0.0, 1.6]])
+TRI = np.array([[1.1, 0.1, -0.2], [0.3, 0.9, 0.15], [-0.1, 0.25, 1.3]])
+
+
+@pytest.mark.parametrize("sorted_", [False, True])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_plan_with_general_cells(torch, q, oracle, dtype, sorted_):
+    """A plan holding tables with general cells (hexagonal, triclinic) and an
+    orthorhombic one: every task runs the VGH-family kernel (V, G, and L as
+    the trace of the Cartesian Hessian).  Against the FP64 oracle (the
+    general-cell oracle for the lattices) at the VGL bars; the general tables
+    equal their own single-table spline_eval_vgl under the plan's shape bit
+    for bit; a locality-ordered plan equals the plain one bit for bit."""
+    specs = [((8, 9, 10), 64, 700), ((10, 8, 8), 128, 333), ((9, 9, 9), 32, 64)]
+    lats = [HEX, TRI, None]
+    rng = np.random.default_rng(19)
+    sp, pos, coefs = [], [], []
+    for (grid, N, B), lat in zip(specs, lats):
+        c = rng.uniform(-1, 1, grid + (N,))
+        s = q.Spline(grid, c, dtype)
+        if lat is not None:
+            s.set_lattice(lat)
+        frac = rng.uniform(-1, 2, (B, 3))
+        sp.append(s)
+        pos.append(torch.from_numpy(frac @ lat if lat is not None else frac).cuda())
+        coefs.append(c)
+    _say("case general plan", dtype, "sorted", sorted_)
+    plan = q.Plan(sp, pos, tune_reps=2, sorted=sorted_)
+    info = plan.info()
+    _say("plan info", info)
+    outs = [[t.clone() for t in o] for o in plan.launch()]
+    torch.cuda.synchronize()
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for s, p, o, c, lat in zip(sp, pos, outs, coefs, lats):
+        table = c if dtype == "f64" else oracle.dequantize(c, "f32")[0]
+        pn = p.cpu().numpy()
+        if lat is not None:
+            V, G, H = oracle.eval_vgh(s.grid, table, pn, lat)
+            ref = (V, G, H[:, 0] + H[:, 3] + H[:, 5])
+            s.set_vgh_tile(info["tile"])
+            single = s.eval_vgl(p)
+            torch.cuda.synchronize()
+            _same(o, single)
+        else:
+            ref = oracle.eval_vgl(s.grid, table, pn)
+        for name, g_, r_ in zip("VGL", o, ref):
+            e = oracle.rel_err(g_.double().cpu().numpy(), r_)
+            assert e <= tol, (name, e)
+    if sorted_:
+        # per-orbital arithmetic does not depend on the shape (the tuner
+        # checks that bitwise), so the plain plan's default shape gives the
+        # same bits
+        plain = q.Plan(sp, pos, tune_reps=0)
+        _same([t for o in outs for t in o], [t for o in plain.launch() for t in o])
