@@ -298,19 +298,27 @@ int spline_det_update(void* ainv_dev, int32_t n, int64_t walker_stride, const in
  *       a_k . q - t^T S^-1 y,  t_i = a_k . phi_i,  y_i = a_{k_i} . q,
  *     for q = V (out[count]) or q = V, Gx, Gy, Gz, L (out[count][5]): the
  *     determinant ratio and derivative sums against the current matrix.  k
- *     must not be a pending electron of its walker (flush once per sweep).
- *     A slot with k or its walker out of range gets NaN.
+ *     may be a pending electron of its walker: row k of the current inverse
+ *     then carries the correction of its replaced column, t_i - [k_i == k].
+ *     A slot with k or its walker out of range, or whose walker is marked
+ *     (below), gets NaN.
  *   spline_dlu_accept: slots with k in [0, n) append their move (phi = V[s])
  *     and border S^-1 (the Schur complement is the ratio); k = -1 marks a
- *     rejected move, and a slot whose walker is out of range is skipped.  At most `delay` accept calls between flushes
- *     (SPL_EINVAL otherwise); a walker may appear once per call.
+ *     rejected move, and a slot whose walker is out of range is skipped.  At
+ *     most `delay` accept calls between flushes (SPL_EINVAL otherwise); a
+ *     walker may appear once per call.  The pending electrons of a walker
+ *     must be distinct: an accept of an electron that is already pending is
+ *     not applied and marks the walker, whose ratios are NaN from then on (a
+ *     flush keeps the mark; spline_dlu_create clears it) -- flush before
+ *     moving an electron a second time.
  *   spline_dlu_accept_ratio: one call for the accept of the previous move
  *     (k_acc[s], V_acc[s], as spline_dlu_accept) followed by the ratio of the
  *     next proposal (k[s], V/G/L[s], as spline_dlu_ratio) in slot s, for a
  *     step loop that evaluates the next proposal's orbitals before the
  *     previous move's accept; results equal the two calls bit for bit, in
  *     one launch (two when S^-1 does not fit in LDS).  k_acc[s] < 0: nothing
- *     to accept; k[s] must not be pending after the accept.
+ *     to accept.  If that accept is refused as a second move of a pending
+ *     electron, the slot's ratio is NaN.
  *   spline_dlu_flush: A^-1 -= (A^-1 Phi - Q) S^-1 R for every walker (R: rows
  *     k_l of A^-1, Q: columns e_{k_l}), then no move is pending.  ainv must
  *     hold the inverses of all `walkers` walkers of the workspace.

@@ -99,8 +99,12 @@ def delayed_ratio(ainv0: np.ndarray, phis, ks, k: int, q: np.ndarray) -> np.ndar
     ainv0 (the delayed update of the paper's outlook, built on the Woodbury
     identity): with a_i the rows of ainv0, phis[i] the orbital vector accepted
     for electron ks[i], S[i][l] = a_{ks[i]} . phis[l], t[i] = a_k . phis[i]
-    and y[i] = a_{ks[i]} . q, the result is a_k . q - t^T S^-1 y.  q: [n] or
-    [m, n] (one result per row).  k must not be among ks."""
+    - [ks[i] == k] and y[i] = a_{ks[i]} . q, the result is a_k . q -
+    t^T S^-1 y: q dotted with row k of the current inverse ainv0 - (ainv0 Phi
+    - Q) S^-1 R (the Woodbury form; the [ks[i] == k] term is row k of Q, so an
+    electron that is itself pending gets its ratio against the current
+    matrix).  q: [n] or [m, n] (one result per row).  The electrons ks must
+    be distinct."""
     a = np.asarray(ainv0, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     x = q @ a[k]
@@ -110,7 +114,7 @@ def delayed_ratio(ainv0: np.ndarray, phis, ks, k: int, q: np.ndarray) -> np.ndar
     P = np.asarray(phis, dtype=np.float64).reshape(j, -1)
     R = a[list(ks)]
     S = R @ P.T
-    t = P @ a[k]
+    t = P @ a[k] - (np.asarray(ks) == k).astype(np.float64)
     y = q @ R.T  # [..., j]
     return x - y @ np.linalg.solve(S.T, t)
 

@@ -285,15 +285,25 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
         const float* const row[1] = {A + (int64_t)k_r * n};
         dlu_copy_rows<1>(ar, row, n);
     }
+    const bool poisoned = cnt[1] != 0;  // an earlier accept could not be represented
     const float* Sr = a.stage_sinv ? Ss : Sinv;  // row stride d either way
     __syncthreads();
+
+    // A second move of an electron that is already pending cannot be held
+    // (the pending moves must be distinct electrons): it is not applied and
+    // the walker is marked, so that its ratios are NaN from then on.
+    bool dup = false;
+    if (acc_ok)
+        for (int l = 0; l < j; ++l) dup = dup || Ks[l] == k_a;
+    if (dup && tid == 0) cnt[1] = 1;
+    const bool acc_do = acc_ok && !dup;
 
     int jr = j;  // pending moves the ratio sees
     // Both steps: the ratio's dots against the moves pending before this step
     // do not depend on the accept, so they share its pass over the rows.
-    const bool both = acc_ok && j < d && rat_ok;  // the host keeps accepts between flushes <= d
+    const bool both = acc_do && j < d && rat_ok;  // the host keeps accepts between flushes <= d
     if (both) dlu_dots_both<NQ>(a, A, st, j, Ks, aa, qa, xa, ta, ya, ar, qs, x, t, y);
-    if (acc_ok && j < d) {
+    if (acc_do && j < d) {
         if (!both) dlu_dots<1>(a, A, st, j, Ks, aa, qa, xa, ta, ya);
         __syncthreads();
         if (tid < j) {
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
         __syncthreads();
     }
     if constexpr (RATIO) {
-        if (!rat_ok) {
+        if (!rat_ok || poisoned || dup) {
             if (tid < NQ) a.out[s * NQ + tid] = __builtin_nanf("");
             return;
         }
@@ -356,6 +366,11 @@ __global__ __launch_bounds__(kDThreads) void dlu_step_kernel(DluArgs a)
             }
             dlu_lds_dots(p1, p2, dst, NQ + 1, n);
         }
+        __syncthreads();
+        // A pending electron's row of the current inverse carries the
+        // correction of its replaced column: t_i - [k_i == k] (the Woodbury
+        // form of row k of A^-1, Q = columns e_{k_i}).
+        if (tid < jr && Ks[tid] == k_r) t[tid] -= 1.f;
         __syncthreads();
         if (tid < jr) {  // u = t^T S^-1
             float v = 0.f;
@@ -822,10 +837,15 @@ static size_t dlu_mfma_lds(int n)
     return sizeof(float) * (16 * (size_t)(dlu_mfma_ldp(n) + dlu_mfma_ldm(n)) + kMfmaWaves * 16 * 20) + 16 * 4;
 }
 
-__global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W)
+// Clears the pending-move count of every walker (and, at creation, the mark
+// left by an accept that could not be represented).
+__global__ void dlu_clear_kernel(float* ws, DluLayout L, int64_t W, int32_t marks)
 {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w < W) reinterpret_cast<int32_t*>(ws + w * L.stride + L.cnt)[0] = 0;
+    if (w >= W) return;
+    int32_t* c = reinterpret_cast<int32_t*>(ws + w * L.stride + L.cnt);
+    c[0] = 0;
+    if (marks) c[1] = 0;
 }
 
 }  // namespace qs
@@ -882,7 +902,7 @@ int spline_dlu_create(int32_t n, int32_t delay, int64_t walkers, void* ws_dev, s
     h->accepts = 0;
     QS_HIP(hipGetDevice(&h->device));
     hipLaunchKernelGGL(dlu_clear_kernel, dim3((unsigned)((walkers + 255) / 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), h->ws, h->L, walkers);
+                       static_cast<hipStream_t>(stream), h->ws, h->L, walkers, 1);
     QS_HIP(hipGetLastError());
     *out = h;
     return SPL_OK;
@@ -1030,7 +1050,7 @@ int spline_dlu_flush(spline_dlu_t* h, float* ainv, int64_t walker_stride, void* 
                                    dim3(W, nb, nb), dim3(kDThreads), params, 0, st));
         }
     }
-    hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers);
+    hipLaunchKernelGGL(dlu_clear_kernel, dim3((W + 255) / 256), dim3(256), 0, st, h->ws, h->L, h->walkers, 0);
     QS_HIP(hipGetLastError());
     h->accepts = 0;
     return SPL_OK;

@@ -253,3 +253,70 @@ def test_fused_accept_ratio_equals_separate_calls(torch, q, n, delay, walkers, v
     d1.flush(a1)
     d2.flush(a2)
     np.testing.assert_array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+
+
+def test_pending_electrons(torch, q):
+    """A proposal for an electron that is itself pending gets its ratio (and
+    derivative sums) against the current matrix -- row k of the Woodbury
+    inverse, whose t carries the [k_i == k] correction -- checked against the
+    oracle and against numpy's inverse of the matrix with the pending columns
+    in place.  A second accept of a pending electron cannot be held: it is
+    not applied, the walker is marked and its ratios are NaN (a flush keeps
+    the mark, a new workspace clears it); other walkers are unaffected."""
+    from oracle import det
+
+    n, delay, walkers = 96, 8, 3
+    rng = np.random.default_rng(77)
+    A = np.eye(n) + rng.normal(size=(walkers, n, n)) * (0.3 / np.sqrt(n))
+    inv0 = np.linalg.inv(A).astype(np.float32)
+    ks = np.stack([rng.permutation(n)[:4] for _ in range(walkers)]).astype(np.int32)
+    phis = (A[:, :, 0][:, None, :] * 0 + rng.normal(size=(walkers, 4, n)) * 0.2).astype(np.float32)
+    cur = A.copy()
+    for w in range(walkers):
+        for i in range(4):
+            phis[w, i] += A[w][:, ks[w, i]].astype(np.float32)
+            cur[w][:, ks[w, i]] = phis[w, i]
+    a_d = torch.from_numpy(inv0.copy()).cuda()
+    dl = q.DelayedUpdate(n, delay, walkers)
+    for i in range(4):
+        dl.accept(a_d, torch.from_numpy(np.ascontiguousarray(ks[:, i])).cuda(),
+                  torch.from_numpy(np.ascontiguousarray(phis[:, i])).cuda())
+    # ratios with derivatives for the electron accepted second (pending)
+    kp = np.ascontiguousarray(ks[:, 1])
+    Vq = (rng.normal(size=(walkers, n)) / np.sqrt(n)).astype(np.float32)
+    Gq = rng.normal(size=(walkers, 3, n)).astype(np.float32)
+    Lq = rng.normal(size=(walkers, n)).astype(np.float32)
+    D = dl.ratio(a_d, torch.from_numpy(kp).cuda(), torch.from_numpy(Vq).cuda(), torch.from_numpy(Gq).cuda(),
+                 torch.from_numpy(Lq).cuda()).cpu().numpy().astype(np.float64)
+    for w in range(walkers):
+        qv = np.vstack([Vq[w], Gq[w], Lq[w]]).astype(np.float64)
+        ref = det.delayed_ratio(inv0[w].astype(np.float64), phis[w].astype(np.float64), list(ks[w]), int(kp[w]), qv)
+        direct = qv @ np.linalg.inv(cur[w])[kp[w]]
+        sc = np.abs(qv) @ np.abs(np.linalg.inv(cur[w])[kp[w]]) + 1.0
+        assert np.max(np.abs(D[w] - ref) / sc) < TOL, w
+        assert np.max(np.abs(D[w] - direct) / sc) < TOL, w
+    # a second accept of a pending electron, for walker 0 only
+    kdup = np.array([ks[0, 2], -1, -1], dtype=np.int32)
+    dl.accept(a_d, torch.from_numpy(kdup).cuda(), torch.from_numpy(Vq).cuda())
+    k0 = np.array([ks[0, 3], ks[1, 3], ks[2, 3]], dtype=np.int32)
+    r = dl.ratio(a_d, torch.from_numpy(k0).cuda(), torch.from_numpy(Vq).cuda()).cpu().numpy()
+    assert np.isnan(r[0]) and np.isfinite(r[1:]).all()
+    for w in (1, 2):
+        ref = det.delayed_ratio(inv0[w].astype(np.float64), phis[w].astype(np.float64), list(ks[w]), int(k0[w]),
+                                Vq[w].astype(np.float64))
+        assert abs(r[w] - ref) / (np.abs(Vq[w]) @ np.abs(np.linalg.inv(cur[w])[k0[w]]) + 1.0) < TOL
+    # the fused call whose accept is the duplicate: NaN for that slot
+    kdup2 = np.array([ks[0, 0], -1, -1], dtype=np.int32)
+    r2 = dl.accept_ratio(a_d, torch.from_numpy(kdup2).cuda(), torch.from_numpy(Vq).cuda(),
+                         torch.from_numpy(k0).cuda(), torch.from_numpy(Vq).cuda()).cpu().numpy()
+    assert np.isnan(r2[0]) and np.isfinite(r2[1:]).all()
+    dl.flush(a_d)
+    r3 = dl.ratio(a_d, torch.from_numpy(k0).cuda(), torch.from_numpy(Vq).cuda()).cpu().numpy()
+    assert np.isnan(r3[0]) and np.isfinite(r3[1:]).all()
+    # the flushed inverses of the unmarked walkers hold their four moves
+    got = a_d.cpu().numpy().astype(np.float64)
+    for w in (1, 2):
+        assert np.max(np.abs(got[w] @ cur[w] - np.eye(n))) < 1e-3
+    dl2 = q.DelayedUpdate(n, delay, walkers)  # a new workspace: no marks
+    r4 = dl2.ratio(a_d, torch.from_numpy(k0).cuda(), torch.from_numpy(Vq).cuda()).cpu().numpy()
+    assert np.isfinite(r4).all()

@@ -168,6 +168,16 @@ def test_delayed_update_matches_direct_inverses(oracle):
     new = det.delayed_flush(A0inv, phis, ks)
     want = np.linalg.inv(det.slater_matrix(grid, coefs, R2))
     assert np.max(np.abs(new - want)) < 1e-8 * np.max(np.abs(want))
+    # proposals for electrons that are themselves pending: the ratio against
+    # the current matrix (row k of its inverse), which needs the correction
+    for k in ks[:4]:
+        rnew = rng.random(3)
+        V, G, L = oracle.eval_vgl(grid, coefs, rnew[None])
+        q = np.vstack([V[0], G[0], L[0]])
+        want = q @ np.linalg.inv(det.slater_matrix(grid, coefs, R2))[k]
+        got = det.delayed_ratio(A0inv, phis, ks, int(k), q)
+        scale = np.abs(q) @ np.abs(np.linalg.inv(det.slater_matrix(grid, coefs, R2))[k])
+        assert np.max(np.abs(got - want) / scale) < 1e-9, k
 
 
 def test_general_cell_ratio(oracle):
