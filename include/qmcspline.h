@@ -53,8 +53,17 @@ extern "C" {
  * power-of-two per-orbital scale s_m = 2^ceil(log2 max_j |c_jm|) (1 for an
  * all-zero orbital), rounded to nearest even directly from FP64; FP16 keeps
  * subnormals.  Evaluation accumulates in FP32 (FP64 for SPL_F64) and
- * multiplies the five sums by s_m at the end. */
-typedef enum { SPL_F64 = 0, SPL_F32 = 1, SPL_BF16 = 2, SPL_F16 = 3 } spline_dtype;
+ * multiplies the five sums by s_m at the end.  The last two names only widen
+ * the type to every int32 value, so that any value a caller passes is well
+ * defined (and rejected with SPL_EINVAL unless it is one of the four). */
+typedef enum {
+    SPL_F64 = 0,
+    SPL_F32 = 1,
+    SPL_BF16 = 2,
+    SPL_F16 = 3,
+    SPL_DTYPE_LOW_ = -0x7fffffff - 1,
+    SPL_DTYPE_HIGH_ = 0x7fffffff
+} spline_dtype;
 
 enum {
     SPL_OK = 0,
@@ -392,7 +401,9 @@ int spline_get_tile(const spline_t* s, spline_tile* tile);
  * With a non-NULL cache_path, matching entries (key: device arch, grid,
  * n_orb, store, B bucket; " V" appended for value only) are used without
  * searching, and new results are appended; an unreadable or corrupt cache is
- * ignored.  Outputs V/G/L are overwritten.  For a table with a general
+ * ignored.  cache_path == NULL takes the file named by the environment
+ * variable QMCSPLINE_TUNE_CACHE when it is set and not empty (no cache
+ * otherwise); the same holds for spline_autotune_sorted.  Outputs V/G/L are overwritten.  For a table with a general
  * lattice it tunes the general-cell VGL kernels instead (no cache). */
 int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, void* V, void* G, void* L,
                     int32_t reps, const char* cache_path, void* stream, spline_tile* chosen);

@@ -79,6 +79,11 @@ struct PlanArgs {
 };
 constexpr int kPlanSegs = 8;
 
+// Task list of a plan for positions-per-task pb (plan_host.cpp): tables with
+// the widest rows first (largest tasks first, the narrow ones fill the
+// tail), each table's positions in blocks of at most pb; empty for pb < 1.
+std::vector<PlanTask> plan_tasks(const int64_t* B, const int64_t* row_bytes, int32_t n, int pb);
+
 // One compiled kernel variant.
 struct Variant {
     spline_dtype store;
@@ -157,6 +162,9 @@ int tune_kind(const spline_s* s, bool vgl, const std::vector<spline_tile>& cands
               spline_tile* best);
 std::string tune_key(const spline_s* s, int64_t B);
 bool cache_lookup(const char* path, const std::string& key, spline_tile* t);
+// The tuning cache to use: the given path, else $QMCSPLINE_TUNE_CACHE when
+// set and not empty, else none.
+const char* tune_cache_path(const char* given);
 
 }  // namespace qs
 

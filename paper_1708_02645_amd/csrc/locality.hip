@@ -412,6 +412,7 @@ int spline_autotune_sorted(spline_t* s, const double* pos_dev, int64_t B, void* 
     if (s->general) return fail(SPL_EUNSUPPORTED, "general cells use the VGH-family tile (spline_autotune_vgh)");
     if (reps < 1) reps = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    cache_path = tune_cache_path(cache_path);
     const std::string key = tune_key(s, B) + " sorted", vkey = key + " V";
     spline_tile tv{}, tn{};
     const bool have_v = cache_path && cache_lookup(cache_path, key, &tv) && check_tile(s, &tv, true) == SPL_OK;

@@ -84,20 +84,25 @@ struct spline_plan_s {
 
 namespace qs {
 
-// Builds the task list for positions-per-task pb: tables with the widest
-// rows first (largest tasks first, the narrow ones fill the tail).
+std::vector<PlanTask> plan_tasks(const int64_t* B, const int64_t* row_bytes, int32_t n, int pb)
+{
+    std::vector<int32_t> order((size_t)std::max(n, 0));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return row_bytes[a] > row_bytes[b]; });
+    std::vector<PlanTask> tasks;
+    if (pb < 1) return tasks;
+    for (int32_t t : order)
+        for (int64_t f = 0; f < B[t]; f += pb)
+            tasks.push_back(PlanTask{t, (int32_t)std::min<int64_t>(pb, B[t] - f), f});
+    return tasks;
+}
+
 static std::vector<PlanTask> make_tasks(const spline_plan_s* p, int pb)
 {
-    std::vector<int32_t> order(p->tabs.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return p->tabs[a]->layout.row_bytes > p->tabs[b]->layout.row_bytes;
-    });
-    std::vector<PlanTask> tasks;
-    for (int32_t t : order)
-        for (int64_t f = 0; f < p->B[t]; f += pb)
-            tasks.push_back(PlanTask{t, (int32_t)std::min<int64_t>(pb, p->B[t] - f), f});
-    return tasks;
+    std::vector<int64_t> rb;
+    for (const spline_s* s : p->tabs) rb.push_back(s->layout.row_bytes);
+    return plan_tasks(p->B.data(), rb.data(), (int32_t)p->tabs.size(), pb);
 }
 
 // A candidate plan kernel: its function, staged weights per position, shape.

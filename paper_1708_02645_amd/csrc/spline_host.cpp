@@ -79,8 +79,8 @@ static int elem_bytes(spline_dtype s)
     case SPL_F32: return 4;
     case SPL_BF16:
     case SPL_F16: return 2;
+    default: return 0;  // not a storage type
     }
-    return 0;
 }
 
 bool mul_ok(int64_t a, int64_t b, int64_t* out)
@@ -270,6 +270,8 @@ int spline_pack_host(const spline_grid* grid, int32_t n_orb, const double* coefs
                     }
                     break;
                 }
+                default:
+                    break;  // unreachable: compute_layout rejected the type
                 }
             }
         }
@@ -598,6 +600,13 @@ std::string tune_key(const spline_s* s, int64_t B)
     return k.str();
 }
 
+const char* tune_cache_path(const char* given)
+{
+    if (given) return given;
+    const char* env = std::getenv("QMCSPLINE_TUNE_CACHE");
+    return env && env[0] ? env : nullptr;
+}
+
 bool cache_lookup(const char* path, const std::string& key, spline_tile* t)
 {
     std::ifstream f(path);
@@ -694,6 +703,7 @@ extern "C" int spline_autotune(spline_t* s, const double* pos_dev, int64_t B, vo
     if (reps < 1) reps = 1;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (s->general) return vgh_autotune(s, 1 /* general-cell VGL */, pos_dev, B, V, G, L, reps, st, chosen);
+    cache_path = tune_cache_path(cache_path);
     const std::string key = tune_key(s, B), vkey = key + " V";
     spline_tile tv{}, tn{};
     const bool have_v = cache_path && cache_lookup(cache_path, key, &tv) && check_tile(s, &tv, true) == SPL_OK;
