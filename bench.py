@@ -98,6 +98,124 @@ def time_steps(torch, fn, steps: int, warmup: int):
     return med, wall
 
 
+def _read_csv(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_per_dispatch(rows, counter):
+    """{dispatch id: (kernel name, grid work-items, summed value)} for one counter."""
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, grid, v = out.get(d, (r["Kernel_Name"], int(r.get("Grid_Size") or 0), 0.0))
+        out[d] = (name, grid, v + float(r["Counter_Value"]))
+    return out
+
+
+def summarize_counters(d: str) -> int:
+    """Writes profiles/<form>_traffic.json from a counter session in d:
+    d/bench.json (the bench line of the counted run, for the tile shapes),
+    d/fetch and d/write (FETCH_SIZE, WRITE_SIZE over that run), d/cfetch and
+    d/cwrite (the same counters over --copy-probe 2048), d/copy4g.json (the
+    line of --copy-probe 4096) and d/trace (a --kernel-trace run, for the
+    kernels' average durations).  Counter values are KiB per dispatch; each is
+    scaled by what the counter reads for the plain copy of known size."""
+    import glob
+
+    import numpy as np
+
+    line = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
+    one = lambda sub: glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)[0]  # noqa: E731
+    fetch = _counter_per_dispatch(_read_csv(one("fetch")), "FETCH_SIZE")
+    write = _counter_per_dispatch(_read_csv(one("write")), "WRITE_SIZE")
+    cf = _counter_per_dispatch(_read_csv(one("cfetch")), "FETCH_SIZE")
+    cw = _counter_per_dispatch(_read_csv(one("cwrite")), "WRITE_SIZE")
+    copy_bytes = 2048 << 20
+    # the six device copies of the probe (the fill before them reads nothing)
+    cfk = [v for _, _, v in cf.values() if v * 1024 > copy_bytes / 4]
+    cwk = [cw[k][2] for k in sorted(cw) if cf.get(k, ("", 0, 0.0))[2] * 1024 > copy_bytes / 4]
+    fetch_scale = copy_bytes / (float(np.median(cfk)) * 1024)
+    write_scale = copy_bytes / (float(np.median(cwk)) * 1024)
+    trace_rows = _read_csv(glob.glob(os.path.join(d, "trace", "**", "*kernel_trace.csv"), recursive=True)[0])
+    copy4 = json.loads(open(os.path.join(d, "copy4g.json")).read().strip().splitlines()[-1])
+    B, N = line["config"]["positions"], line["config"]["norb"]
+    forms = line["forms"]
+
+    def name(kind, t, *rest):
+        if kind == "vgh":
+            return "void qs::vgh_kernel<(spline_dtype)1, %d, %d, %d, %d>(qs::VghArgs)" % (t[0], t[1], t[2], rest[0])
+        return "void qs::eval_kernel<(spline_dtype)1, %d, %d, %d, true, %s>(qs::EvalArgs)" % (
+            t[0], t[1], t[2], "true" if rest[0] else "false")
+
+    specs = [
+        ("vgl_f32_80cube_n384", name("eval", line["config"]["tile"], False), line["config"]["tile"], 276,
+         KERNEL_SOURCES, "80^3 grid, N=384, FP32 table, 196608 positions"),
+        ("ratio_vgl_f32_80cube_n384", name("eval", line["config"]["tile"], True), line["config"]["tile"],
+         64 * 4 + 4 + 20.0 / N, KERNEL_SOURCES, "80^3 grid, N=384, FP32 table, 196608 positions"),
+        ("vgh_f32_80cube_n384", name("vgh", forms["f32_vgh_hexagonal"]["tile"], 0), forms["f32_vgh_hexagonal"]["tile"],
+         64 * 4 + 40, VGH_SOURCES, "80^3 grid, N=384, FP32 table, 196608 positions (orthorhombic and hexagonal cells)"),
+        ("vgl_sorted_f32_80cube_n384", name("eval", forms["f32_locality_sorted"]["tile"], False),
+         forms["f32_locality_sorted"]["tile"], 276, SORTED_SOURCES,
+         "80^3 grid, N=384, FP32 table, 196608 positions, locality-ordered (positions sorted on the device first)"),
+    ]
+    for form, kname, tile, bpu, srcs, workload in specs:
+        sorted_form = "sorted" in form
+        # a locality-ordered launch follows the sort's scatter kernel; a plain one does not
+        ids = sorted(k for k, (n_, g_, _) in fetch.items() if n_ == kname and g_ == -(-B // tile[3]) * 256)
+
+        def after_scatter(k, table):
+            prev = max((j for j in table if j < k), default=None)
+            return prev is not None and "loc_scatter" in table[prev][0]
+
+        ids = [k for k in ids if after_scatter(k, fetch) == sorted_form]
+        wids = sorted(k for k, (n_, g_, _) in write.items() if n_ == kname and g_ == -(-B // tile[3]) * 256
+                      and after_scatter(k, write) == sorted_form)
+        if not ids or not wids:
+            print("summarize: no dispatches of %s" % kname, file=sys.stderr)
+            continue
+        fk = [fetch[k][2] for k in ids]
+        wk = [write[k][2] for k in wids]
+        rd = float(np.mean(fk)) * 1024 * fetch_scale
+        wr = float(np.mean(wk)) * 1024 * write_scale
+        durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace_rows if r["Kernel_Name"] == kname
+                and int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0) == -(-B // tile[3]) * 256]
+        alg = B * N * bpu
+        out = {"kernel": kname, "tile": list(tile), "workload": workload, "kernel_hash": kernel_hash(srcs),
+               "fetch_size_kib_per_dispatch": fk, "write_size_kib_per_dispatch": wk,
+               "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cfk, "copy_write_kib": cwk,
+               "fetch_scale": fetch_scale, "write_scale": write_scale,
+               "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr, "hbm_bytes_per_launch": rd + wr,
+               "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (rd + wr) / alg,
+               "avg_kernel_ns_rocprof": float(np.mean(durs)) if durs else None,
+               "kernel_trace_launches": len(durs),
+               "hbm_GBs_measured": (rd + wr) / float(np.mean(durs)) if durs else None,
+               "plain_device_copy_4GiB": copy4,
+               "note": "FETCH_SIZE counts reads the Infinity Cache serves as well as DRAM reads",
+               "commands": ["cd /tmp && export TMPDIR=/tmp",
+                            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/fetch -o fetch -- python3 "
+                            "<repo>/bench.py --no-forms --no-ragged --no-cpu-baseline --mlp-steps 0 --steps 3 "
+                            "--warmup 1 > <out>/bench.json",
+                            "rocprofv3 --pmc WRITE_SIZE (the same)",
+                            "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE --output-format csv -d <out>/cfetch|cwrite -- "
+                            "python3 <repo>/bench.py --copy-probe 2048",
+                            "python3 <repo>/bench.py --copy-probe 4096 > <out>/copy4g.json",
+                            "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o trace -- "
+                            "python3 <repo>/bench.py --mlp-steps 300 --no-cpu-baseline  (the default bench: "
+                            "same steps, warm-ups and tuned tiles; the surrogate trains 300 steps; the duration "
+                            "averages every launch of the kernel on this batch, cold-cache ones included)",
+                            "python3 <repo>/bench.py --summarize-counters <out>"]}
+        with open(os.path.join(ROOT, "profiles", form + "_traffic.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        print("%s: %d/%d dispatches, traffic %.3f of algorithmic, %s ns" % (
+            form, len(fk), len(wk), out["traffic_over_algorithmic"], out["avg_kernel_ns_rocprof"]))
+    return 0
+
+
 MLP_FLOP_PER_POS = 2 * 5 * (96 * 256 + 256 * 256 + 256 * 192)
 PEAK_FP32_VECTOR_TFLOPS = 78.6  # unpacked FMA (packed FP32 is not used)
 PEAK_BF16_TFLOPS = 2500.0
@@ -252,10 +370,14 @@ def main() -> int:
                     help="cw,nch,lpp,pb for the FP32 locality-ordered form (skips its autotuner)")
     ap.add_argument("--no-tune-cache", dest="use_tune_cache", action="store_false",
                     help="search tile shapes afresh instead of reading the committed tuning cache")
+    ap.add_argument("--summarize-counters", type=str, default="", metavar="DIR",
+                    help="only write profiles/*_traffic.json from a rocprofv3 counter session in DIR")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        return summarize_counters(args.summarize_counters)
     if args.copy_probe:
         import torch
 
