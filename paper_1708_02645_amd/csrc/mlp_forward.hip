@@ -6,21 +6,23 @@
 // 256).  Operand layout of the instruction (lane l, g = l/16, c = l%16):
 // A[c][8g..8g+7], B[8g..8g+7][c], C[4g..4g+3][c].  Each layer is computed
 // transposed, H^T[unit][pos] = sum_k W[unit][k] Act[pos][k]:
-//  - weight rows are the A operand, read from global memory a few K steps
+//  - weight rows are the A operand, read from global memory one K step
 //    ahead of use (280 KB in all, L2-resident).  The BF16 weights are kept
 //    in fragment order, so one wave's operand load is one contiguous 1 KB
 //    block; row-major rows made it 16 half-used cache lines, and those loads
 //    were the kernel's bound;
 //  - the layer input, a [stream][16][256] BF16 tile in LDS shared by the
 //    four waves (16-byte chunks XOR-swizzled by row), gives the B operands,
-//    read one K step ahead.
+//    each stream's read one K step ahead.
 // Each stream (value, d/dx, d/dy, d/dz, Laplacian) is its own product, so
 // the five accumulators of a (unit, position) pair sit in the same lane and
 // slot and the forward-mode SiLU combines them in registers; a lane then
-// holds four consecutive units of one position and writes them to the other
-// tile with one 8-byte store per stream.  Two tiles alternate as layer input
-// and output (80 KB per workgroup), so two workgroups share a CU: two waves
-// per SIMD, one's vector work hiding behind the other's matrix products.
+// holds four consecutive units of one position and writes them back with one
+// 8-byte store per stream.  One tile serves as every layer's input and
+// output (a barrier separates the last operand reads from the epilogue's
+// writes), 40 KB per workgroup, and the kernel is held to 168 registers (up
+// to 192 outputs): three workgroups share a CU, three waves per SIMD, so two
+// waves' loads and vector work hide behind the third's matrix products.
 #include "mlp_kernels.hpp"
 
 #include "common.hpp"
@@ -48,7 +50,7 @@ template <int KSTEPS, int NB>
 __device__ inline void layer_products(const __bf16* __restrict__ xt, const __bf16* __restrict__ W, int blk0,
                                       int blocks, int g, int c, f32x4 (&acc)[kStreams][NB])
 {
-    constexpr int R = 4;  // ring depth: weight fragments of step t+R-1 are loaded at step t
+    constexpr int R = 2;  // ring depth: weight fragments of step t+1 are loaded at step t
     // W is in fragment order: fragment (blk, t) is 512 values, lane l's 8 at 8l.
     const __bf16* wrow[NB];
 #pragma unroll
@@ -62,16 +64,16 @@ __device__ inline void layer_products(const __bf16* __restrict__ xt, const __bf1
         if (i < KSTEPS)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) ring[i][nb] = *reinterpret_cast<const bf16x8*>(wrow[nb] + 512 * i);
-    bf16x8 x[2][kStreams];
+    bf16x8 x[kStreams];  // one B operand per stream
 #pragma unroll
-    for (int s = 0; s < kStreams; ++s) x[0][s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 8 * g));
+    for (int s = 0; s < kStreams; ++s) x[s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 8 * g));
 #pragma unroll
     for (int s = 0; s < kStreams; ++s)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // The scheduling fences keep each step's loads ahead of its products
-    // (otherwise the scheduler sinks them next to their use and every step
-    // waits for a full L2 or LDS round trip).
+    // The scheduling fences keep each load ahead of the products that follow
+    // it (otherwise the scheduler sinks loads next to their use and every
+    // step waits for a full L2 or LDS round trip).
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < KSTEPS; ++t) {
@@ -79,17 +81,17 @@ __device__ inline void layer_products(const __bf16* __restrict__ xt, const __bf1
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
                 ring[(t + R - 1) % R][nb] = *reinterpret_cast<const bf16x8*>(wrow[nb] + 512 * (t + R - 1));
-        if (t + 1 < KSTEPS)
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s)
-                x[(t + 1) & 1][s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 32 * (t + 1) + 8 * g));
         __builtin_amdgcn_sched_barrier(0);
+        // stream s's operand of step t+1 is read as soon as its products of
+        // step t are issued, so only one operand per stream is live
 #pragma unroll
-        for (int s = 0; s < kStreams; ++s)
+        for (int s = 0; s < kStreams; ++s) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[t % R][nb], x[t & 1][s], acc[s][nb], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
+                acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[t % R][nb], x[s], acc[s][nb], 0, 0, 0);
+            if (t + 1 < KSTEPS) x[s] = *reinterpret_cast<const bf16x8*>(xt + zoff(s, c, 32 * (t + 1) + 8 * g));
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
@@ -123,80 +125,43 @@ __device__ inline void hidden_epilogue(const f32x4 (&acc)[kStreams][NB], const f
     }
 }
 
-// Output epilogue: bias and the per-orbital affine map.  STAGED: the
-// workgroup's outputs (16 positions of V, G and L, 80 rows of nout floats)
-// are first written to LDS, rows padded by 4 floats so a wave's 16 rows fall
-// in distinct banks, then copied to V, G, L as contiguous 16-byte stores (the
-// 16 positions' rows of each output are contiguous in memory).  Otherwise
-// each lane stores four consecutive orbitals of one position directly.
+// Output epilogue: bias and the per-orbital affine map, for output block nb
+// of the wave: q[0] value, q[1..3] gradient, q[4] Laplacian of orbitals
+// n0..n0+3 at the lane's position.
+template <int NB>
+__device__ inline int output_block(const MlpFwdArgs& a, const f32x4 (&acc)[kStreams][NB], const float* b3, int nb,
+                                   int blk0, int g, f32x4v (&q)[kStreams])
+{
+    const int n0 = (blk0 + nb) * 16 + 4 * g;
+    const f32x4v sd = *reinterpret_cast<const f32x4v*>(a.sd + n0);
+    const f32x4v mu = *reinterpret_cast<const f32x4v*>(a.mu + n0);
+    const f32x4v bb = *reinterpret_cast<const f32x4v*>(b3 + n0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        q[0][j] = (acc[0][nb][j] + bb[j]) * sd[j] + mu[j];
+#pragma unroll
+        for (int s = 1; s < kStreams; ++s) q[s][j] = acc[s][nb][j] * sd[j];
+    }
+    return n0;
+}
+
+// Staged outputs: rows of nout floats in the tile, padded by 4 floats so a
+// wave's 16 rows fall in distinct banks.  Two rounds: the 16 value rows and
+// the 16 Laplacian rows (32 rows), then the 48 gradient rows (row 3 pos + d,
+// the order of G in memory); each round needs 48 (nout + 4) floats at most,
+// within the tile for nout up to 208.
 constexpr int kStagePad = 4;
 
-__device__ inline int stage_row(int q, int pos, int nout)
+// Copies `rows` staged rows to dst, where they are one contiguous run (the
+// workgroup's positions are consecutive), in 16-byte pieces taken by
+// consecutive threads.
+__device__ inline void copy_rows(const float* stage, float* dst, int rows, int N, int tid)
 {
-    // q: 0 value, 1..3 gradient components, 4 Laplacian
-    return q == 0 ? pos : (q == 4 ? 4 * kFwdPos + pos : kFwdPos + 3 * pos + (q - 1));
-}
-
-template <int NB, bool STAGED>
-__device__ inline void output_epilogue(const MlpFwdArgs& a, const f32x4 (&acc)[kStreams][NB], const float* b3,
-                                       int64_t b0, int blk0, int blocks, int g, int c, float* stage)
-{
-    const int N = a.nout;
-    const int64_t b = b0 + c;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        if (blk0 + nb >= blocks) continue;
-        const int n0 = (blk0 + nb) * 16 + 4 * g;
-        const f32x4v sd = *reinterpret_cast<const f32x4v*>(a.sd + n0);
-        const f32x4v mu = *reinterpret_cast<const f32x4v*>(a.mu + n0);
-        const f32x4v bb = *reinterpret_cast<const f32x4v*>(b3 + n0);
-        f32x4v q[kStreams];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            q[0][j] = (acc[0][nb][j] + bb[j]) * sd[j] + mu[j];
-#pragma unroll
-            for (int s = 1; s < kStreams; ++s) q[s][j] = acc[s][nb][j] * sd[j];
-        }
-        if constexpr (STAGED) {
-#pragma unroll
-            for (int s = 0; s < kStreams; ++s)
-                *reinterpret_cast<f32x4v*>(stage + stage_row(s, c, N) * (N + kStagePad) + n0) = q[s];
-        } else {
-            if (b >= a.B) continue;
-            __builtin_nontemporal_store(q[0], reinterpret_cast<f32x4v*>(a.V + b * N + n0));
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                __builtin_nontemporal_store(q[1 + d], reinterpret_cast<f32x4v*>(a.G + (3 * b + d) * N + n0));
-            __builtin_nontemporal_store(q[4], reinterpret_cast<f32x4v*>(a.L + b * N + n0));
-        }
-    }
-}
-
-// Copies the staged outputs of positions [b0, b0 + np) to V, G, L: the
-// workgroup's rows of each output are one contiguous run in memory, walked in
-// 16-byte pieces by consecutive threads.
-__device__ inline void store_staged(const MlpFwdArgs& a, const float* stage, int64_t b0, int np, int tid)
-{
-    const int N = a.nout, n4 = N / 4;
-    const int per = np * n4;  // 16-byte pieces per value row block
-    // value rows (np), gradient rows (3 np), Laplacian rows (np)
-    for (int i = tid; i < 5 * per; i += kFwdWaves * 64) {
-        int r, k, srow;
-        float* dst;
-        if (i < per) {
-            r = i / n4, k = i - r * n4, srow = r;
-            dst = a.V + (b0 + r) * N;
-        } else if (i < 4 * per) {
-            const int j = i - per;
-            r = j / n4, k = j - r * n4, srow = kFwdPos + r;
-            dst = a.G + (3 * b0 + r) * N;
-        } else {
-            const int j = i - 4 * per;
-            r = j / n4, k = j - r * n4, srow = 4 * kFwdPos + r;
-            dst = a.L + (b0 + r) * N;
-        }
-        const f32x4v v = *reinterpret_cast<const f32x4v*>(stage + srow * (N + kStagePad) + 4 * k);
-        __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(dst + 4 * k));
+    const int n4 = N / 4;
+    for (int i = tid; i < rows * n4; i += kFwdWaves * 64) {
+        const int r = i / n4, k = i - r * n4;
+        const f32x4v v = *reinterpret_cast<const f32x4v*>(stage + r * (N + kStagePad) + 4 * k);
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(dst + (int64_t)r * N + 4 * k));
     }
 }
 
@@ -236,42 +201,85 @@ __device__ inline void stage_features(const MlpFwdArgs& a, int64_t b0, int tid, 
 }
 
 // NBO: output blocks of 16 orbitals per wave, ceil(nout / 64).  STAGED:
-// outputs go through LDS (needs 80 (nout + 4) floats, within the two tiles).
+// outputs go through the tile (nout up to 208); otherwise each lane stores
+// four consecutive orbitals of one position directly.  Three waves per SIMD
+// where the output epilogue fits in 168 registers without spilling (staged,
+// nout up to 192), else two.
 template <int NBO, bool STAGED>
-__global__ __launch_bounds__(kFwdWaves * 64) void mlp_vgl_kernel(MlpFwdArgs a)
+constexpr int fwd_waves_per_simd = STAGED && NBO < 4 ? 3 : 2;
+
+template <int NBO, bool STAGED>
+__global__ __launch_bounds__(kFwdWaves * 64) __attribute__((
+    amdgpu_waves_per_eu(fwd_waves_per_simd<NBO, STAGED>, fwd_waves_per_simd<NBO, STAGED>))) void mlp_vgl_kernel(MlpFwdArgs a)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 tiles[2 * kTile];
-    __bf16* t0 = tiles;
-    __bf16* t1 = tiles + kTile;
+    __shared__ __attribute__((aligned(16))) __bf16 tile[kTile];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
     const int64_t b0 = (int64_t)blockIdx.x * kFwdPos;
     const MlpOffsets o = mlp_offsets(a.nout);
     constexpr int NBH = kHidden / 16 / kFwdWaves;  // hidden blocks per wave
 
-    stage_features(a, b0, tid, t0);
+    stage_features(a, b0, tid, tile);
     __syncthreads();
     {
         f32x4 acc[kStreams][NBH];
-        layer_products<kIn / 32, NBH>(t0, a.Wh + o.hW1, NBH * w, kHidden / 16, g, c, acc);
-        hidden_epilogue<NBH>(acc, a.P + o.b1, t1, NBH * w, g, c);
+        layer_products<kIn / 32, NBH>(tile, a.Wh + o.hW1, NBH * w, kHidden / 16, g, c, acc);
+        __syncthreads();  // every wave has read its operands before the tile is overwritten
+        hidden_epilogue<NBH>(acc, a.P + o.b1, tile, NBH * w, g, c);
     }
     __syncthreads();
     {
         f32x4 acc[kStreams][NBH];
-        layer_products<kHidden / 32, NBH>(t1, a.Wh + o.hW2, NBH * w, kHidden / 16, g, c, acc);
-        hidden_epilogue<NBH>(acc, a.P + o.b2, t0, NBH * w, g, c);
-    }
-    __syncthreads();
-    const int nblk = a.nout / 16;
-    f32x4 acc[kStreams][NBO];
-    layer_products<kHidden / 32, NBO>(t0, a.Wh + o.hW3, NBO * w, nblk, g, c, acc);
-    float* stage = reinterpret_cast<float*>(tiles);
-    if constexpr (STAGED) __syncthreads();  // every wave has read its last operands from t0
-    output_epilogue<NBO, STAGED>(a, acc, a.P + o.b3, b0, NBO * w, nblk, g, c, stage);
-    if constexpr (STAGED) {
+        layer_products<kHidden / 32, NBH>(tile, a.Wh + o.hW2, NBH * w, kHidden / 16, g, c, acc);
         __syncthreads();
+        hidden_epilogue<NBH>(acc, a.P + o.b2, tile, NBH * w, g, c);
+    }
+    __syncthreads();
+    const int N = a.nout, nblk = N / 16, blk0 = NBO * w;
+    const float* b3 = a.P + o.b3;
+    f32x4 acc[kStreams][NBO];
+    layer_products<kHidden / 32, NBO>(tile, a.Wh + o.hW3, blk0, nblk, g, c, acc);
+    if constexpr (!STAGED) {
+        const int64_t b = b0 + c;
+        if (b >= a.B) return;
+#pragma unroll
+        for (int nb = 0; nb < NBO; ++nb) {
+            if (blk0 + nb >= nblk) continue;
+            f32x4v q[kStreams];
+            const int n0 = output_block<NBO>(a, acc, b3, nb, blk0, g, q);
+            __builtin_nontemporal_store(q[0], reinterpret_cast<f32x4v*>(a.V + b * N + n0));
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                __builtin_nontemporal_store(q[1 + d], reinterpret_cast<f32x4v*>(a.G + (3 * b + d) * N + n0));
+            __builtin_nontemporal_store(q[4], reinterpret_cast<f32x4v*>(a.L + b * N + n0));
+        }
+    } else {
+        float* stage = reinterpret_cast<float*>(tile);
+        const int ld = N + kStagePad;
         const int64_t left = a.B - b0;
-        store_staged(a, stage, b0, left < kFwdPos ? (int)left : kFwdPos, tid);
+        const int np = left < kFwdPos ? (int)left : kFwdPos;
+        __syncthreads();  // every wave has read its last operands
+#pragma unroll
+        for (int nb = 0; nb < NBO; ++nb) {
+            if (blk0 + nb >= nblk) continue;
+            f32x4v q[kStreams];
+            const int n0 = output_block<NBO>(a, acc, b3, nb, blk0, g, q);
+            *reinterpret_cast<f32x4v*>(stage + c * ld + n0) = q[0];
+            *reinterpret_cast<f32x4v*>(stage + (kFwdPos + c) * ld + n0) = q[4];
+        }
+        __syncthreads();
+        copy_rows(stage, a.V + b0 * N, np, N, tid);
+        copy_rows(stage + kFwdPos * ld, a.L + b0 * N, np, N, tid);
+        __syncthreads();
+#pragma unroll
+        for (int nb = 0; nb < NBO; ++nb) {
+            if (blk0 + nb >= nblk) continue;
+            f32x4v q[kStreams];
+            const int n0 = output_block<NBO>(a, acc, b3, nb, blk0, g, q);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) *reinterpret_cast<f32x4v*>(stage + (3 * c + d) * ld + n0) = q[1 + d];
+        }
+        __syncthreads();
+        copy_rows(stage, a.G + 3 * b0 * N, 3 * np, N, tid);
     }
 }
 
@@ -283,7 +291,7 @@ int launch_mlp_forward(const MlpFwdArgs& a, hipStream_t st)
     for (const float* p : {a.V, a.G, a.L})
         if (reinterpret_cast<uintptr_t>(p) & 15) return fail(SPL_EINVAL, "V, G and L must be 16-byte aligned");
     const int nbo = (a.nout / 16 + kFwdWaves - 1) / kFwdWaves;
-    const bool staged = (size_t)5 * kFwdPos * (a.nout + kStagePad) * sizeof(float) <= 2 * kTile * sizeof(__bf16);
+    const bool staged = (size_t)3 * kFwdPos * (a.nout + kStagePad) * sizeof(float) <= kTile * sizeof(__bf16);
     const dim3 grid((unsigned)blocks), block(kFwdWaves * 64);
     switch (nbo * 2 + (staged ? 1 : 0)) {
     case 2: hipLaunchKernelGGL((mlp_vgl_kernel<1, false>), grid, block, 0, st, a); break;

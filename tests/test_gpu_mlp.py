@@ -78,6 +78,23 @@ def test_forward_matches_oracle(torch, q, oracle, small_table):
     assert max(e_emu) <= 2.0 ** -7
 
 
+@pytest.mark.parametrize("N,B", [(16, 1), (64, 17), (128, 31), (160, 5), (208, 19), (240, 33), (256, 47), (256, 16)])
+def test_forward_widths_and_ragged_batches(torch, q, oracle, N, B):
+    """Every output-block count (1 to 4 blocks of 16 per wave, the last wave's
+    share partial at 160), outputs staged through LDS (up to 208 orbitals) and
+    stored directly (240, 256), and batches that end inside a workgroup's 16
+    positions."""
+    net, _ = _net(q, N, seed=11)
+    pos_np = np.random.default_rng(N + B).random((B, 3))
+    _say("case mlp forward N=%d B=%d" % (N, B))
+    got = [t.cpu().numpy() for t in net.forward(torch.from_numpy(pos_np).cuda())]
+    emu = M.forward(net.params_numpy(), pos_np, bf16=True)
+    e = [oracle.rel_err(g, r) for g, r in zip(got, emu)]
+    _say("eps V/G/L = %.2e %.2e %.2e" % tuple(e))
+    assert all(np.isfinite(g).all() for g in got)
+    assert max(e) <= 2.0 ** -7
+
+
 def _set_loss_weights(torch, net, w):
     lay = net.layout
     net.buf[lay.loss_w:lay.loss_w + 12] = torch.tensor(w, dtype=torch.float32).view(torch.uint8).to(net.buf.device)
