@@ -67,6 +67,31 @@ def traffic_from_profiles(tile, name: str = "vgl_f32_80cube_n384") -> float | No
 LAST_TIMING = {}
 
 
+def time_burst_after_idle(torch, fn, n: int = 8, idle_s: float = 0.5, reps: int = 3):
+    """Mean ms per launch of `n` back-to-back launches started after the GPU
+    has been idle for `idle_s` seconds (median over `reps` such bursts): the
+    duration at the clock an idle GPU starts from, before sustained
+    matrix-core load makes the power management lower it.  A spin kernel
+    enqueued first keeps the queue ahead of the host, so the event pair
+    brackets the launches and no host latency."""
+    import numpy as np
+
+    st = torch.cuda.current_stream()
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        time.sleep(idle_s)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1_000_000)
+        a.record(st)
+        for _ in range(n):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / n)
+    return float(np.median(out))
+
+
 def time_steps(torch, fn, steps: int, warmup: int):
     """Runs `warmup` untimed steps, then exactly `steps` timed ones on the
     current stream (the one the library launches on), each between its own
@@ -262,6 +287,7 @@ def bench_mlp(args, q, W, torch, dev, np):
     B = pos.shape[0]
     out = net._out(B)
     ms_net, _ = time_steps(torch, lambda: net.forward(pos, out=out), args.steps, args.warmup)
+    ms_net_idle = time_burst_after_idle(torch, lambda: net.forward(pos, out=out))
     sout = spl.alloc_outputs(B)
     spl.autotune(pos, reps=2, out=sout)
     ms_spl, _ = time_steps(torch, lambda: spl.eval_vgl(pos, out=sout), args.steps, args.warmup)
@@ -285,6 +311,7 @@ def bench_mlp(args, q, W, torch, dev, np):
                       "ms_with_fallback": ms_fb, "speedup_with_fallback_vs_spline": ms_spl / ms_fb})
     beats = [r for r in sweep if r["speedup_with_fallback_vs_spline"] > 1.0]
     tflops = B * MLP_FLOP_PER_POS / (ms_net * 1e-3) / 1e12
+    tflops_idle = B * MLP_FLOP_PER_POS / (ms_net_idle * 1e-3) / 1e12
     _, energy = q.spectral_frequencies(coefs, with_energy=True)
     outside = 1.0 - (float(energy["pairs"].sum()) + energy["k0"]) / energy["total"]
     return {
@@ -305,7 +332,13 @@ def bench_mlp(args, q, W, torch, dev, np):
         "dram_write_GBs_network": units * 20 / (ms_net * 1e-3) / 1e9,
         "roofline_network_kernel": {"bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
                                     "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
-                                    "flop_per_position": MLP_FLOP_PER_POS},
+                                    "flop_per_position": MLP_FLOP_PER_POS,
+                                    "ms_burst_after_idle": ms_net_idle,
+                                    "frac_burst_after_idle": tflops_idle / PEAK_BF16_TFLOPS,
+                                    "note": "frac: median of the timed back-to-back launches, during which "
+                                            "the power management lowers the clock of the sustained "
+                                            "matrix-core load; frac_burst_after_idle: 8 launches after "
+                                            "0.5 s idle, at the clock an idle GPU starts from"},
     }
 
 
