@@ -154,14 +154,22 @@ constexpr int kStagePad = 4;
 
 // Copies `rows` staged rows to dst, where they are one contiguous run (the
 // workgroup's positions are consecutive), in 16-byte pieces taken by
-// consecutive threads.
+// consecutive threads.  Piece i is (row r, column 4k), i = r n/4 + k; the
+// thread's (r, k) advance by a fixed step instead of a division per piece.
 __device__ inline void copy_rows(const float* stage, float* dst, int rows, int N, int tid)
 {
-    const int n4 = N / 4;
-    for (int i = tid; i < rows * n4; i += kFwdWaves * 64) {
-        const int r = i / n4, k = i - r * n4;
+    constexpr int kStep = kFwdWaves * 64;
+    const int n4 = N / 4, dr = kStep / n4, dk = kStep - dr * n4, total = rows * n4;
+    int r = tid / n4, k = tid - r * n4;
+    for (int i = tid; i < total; i += kStep) {
         const f32x4v v = *reinterpret_cast<const f32x4v*>(stage + r * (N + kStagePad) + 4 * k);
         __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(dst + (int64_t)r * N + 4 * k));
+        r += dr;
+        k += dk;
+        if (k >= n4) {
+            k -= n4;
+            ++r;
+        }
     }
 }
 
