@@ -521,7 +521,9 @@ int spline_mlp_select_frequencies(const spline_grid* grid, int32_t n_orb, const 
  * rows 16b..16b+15 and columns 32t..32t+31, is 512 consecutive values (b
  * major), row 16b+c, columns 32t+8g..32t+8g+7 at 8(16g+c).  The buffer is
  * the whole network state: copying it is a checkpoint, and spline_mlp_attach
- * resumes from one. */
+ * resumes from one.  Its last bytes, from meta + 256 to total, are scratch
+ * that spline_mlp_init_output uses (no state), so that call allocates
+ * nothing. */
 typedef struct {
     int64_t n_params;
     int64_t W1, b1, W2, b2, W3, b3;

@@ -44,7 +44,7 @@ static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 static unsigned grid1(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 struct MlpLay {
-    size_t P, M1, M2, Wh, mu, sd, lw, freqs, bin_err, meta, total;
+    size_t P, M1, M2, Wh, mu, sd, lw, freqs, bin_err, meta, stats, total;
 };
 
 static MlpLay mlp_lay(int nout)
@@ -67,6 +67,7 @@ static MlpLay mlp_lay(int nout)
     L.freqs = take((size_t)kFreq * 3 * 4);
     L.bin_err = take((size_t)kMaxBins * kMaxBins * kMaxBins * 4);
     L.meta = take(4 * 8);
+    L.stats = take((size_t)nout * 6 * 8);  // scratch of spline_mlp_init_output
     L.total = at;
     return L;
 }
@@ -436,14 +437,12 @@ int spline_mlp_init_output(spline_mlp_t* m, const float* V, const float* G, cons
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int N = m->nout;
-    double* stats = nullptr;
-    QS_HIP(hipMalloc(&stats, (size_t)N * 6 * sizeof(double)));
+    double* stats = reinterpret_cast<double*>(m->dev + m->lay.stats);
     hipLaunchKernelGGL(mlp_stats_kernel, dim3(grid1(N)), dim3(kThreads), 0, st, V, G, L, B, N, stats);
     std::vector<double> s((size_t)N * 6);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(s.data(), stats, s.size() * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(stats);
     if (e != hipSuccess) return hip_fail(e, "output statistics");
     std::vector<float> mu(N), sd(N);
     double vg = 0, vl = 0;
