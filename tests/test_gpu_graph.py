@@ -1,7 +1,8 @@
 """The kernels of one particle-by-particle step can be captured in a HIP
 graph: the determinant ratio with derivatives, the Jastrow move, the
 Sherman-Morrison update and the Jastrow accept (a slot with k = -1 is a
-rejected move, which both update kernels skip).  The graph is replayed
+rejected move, which both update kernels skip); so can the delayed update,
+the locality-ordered evaluation and the surrogate with its spline fallback.  The graph is replayed
 several times with eager work and synchronisations in between, and every
 replay must equal, bit for bit, the same calls made eagerly on the same
 inputs.  No call in the sequence allocates or clears memory.
@@ -183,3 +184,50 @@ def test_sorted_evaluation_in_a_graph(torch, q):
         torch.cuda.synchronize()
         for a, b in zip(out, ref):
             np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_surrogate_in_a_graph(torch, q):
+    """The surrogate's forward pass and its evaluation with spline fallback
+    (network, routing of the untrusted bins, indexed spline gather) captured
+    in one HIP graph: every replay, with new positions and eager work
+    between replays, equals the eager calls bit for bit, the fallback count
+    included."""
+    rng = np.random.default_rng(12)
+    grid = (12, 12, 12)
+    N = 64
+    G, a, b = W.planewave_params(rng, N)
+    spl = q.Spline(grid, W.fit_planewave_coefs(grid, G, a, b), "f32")
+    freqs, Ws, bs = W.mlp_init(5, seed=4, widths=(96, 256, 256, N))
+    net = q.SurrogateMLP(N, freqs, q.flatten_mlp_params(Ws, bs))
+    dev = torch.device("cuda")
+    net.build_error_map(spl, torch.from_numpy(rng.random((8 * 8 * 8 * 16, 3))).to(dev), bins_per_dim=8)
+    tol = float(np.median(net.bin_errors()))
+    B = 2000
+    pos = torch.from_numpy(rng.random((B, 3))).to(dev)
+    out_f = net._out(B)
+    out_e = net._out(B)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream: the workspace exists before capture
+        net.forward(pos, out=out_f)
+        net.eval_vgl(pos, fallback=spl, tol=tol, out=out_e)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        net.forward(pos, out=out_f)
+        nf = net.eval_vgl(pos, fallback=spl, tol=tol, out=out_e)[3]
+    for rep in range(3):
+        pos.copy_(torch.from_numpy(rng.random((B, 3))).to(dev))
+        for t in out_f + out_e:
+            t.zero_()
+        torch.cuda.synchronize()
+        ref_f = net.forward(pos)  # eager work between replays
+        *ref_e, ref_nf = net.eval_vgl(pos, fallback=spl, tol=tol)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        n_routed = int(nf.cpu()[0])
+        assert n_routed == int(ref_nf.cpu()[0]) and 0 < n_routed < B, (rep, n_routed)
+        for x, y in zip(out_f + out_e, tuple(ref_f) + tuple(ref_e)):
+            np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
