@@ -95,6 +95,28 @@ def test_forward_widths_and_ragged_batches(torch, q, oracle, N, B):
     assert max(e) <= 2.0 ** -7
 
 
+def test_forward_full_batch_sampled(torch, q, oracle):
+    """The 48^3 / N=192 table's surrogate on its full batch (256 walkers x 192
+    electrons = 49152 positions, the benchmark's launch: 3072 workgroups),
+    output map set from the table's VGL: 512 sampled rows against the
+    BF16-model oracle, at the same 2^-7 bar."""
+    grid, N, coefs, _ = W.make_table(5)
+    spl = q.Spline(grid, coefs, "f32")
+    _, Ws, bs = W.mlp_init(5)
+    net = q.SurrogateMLP(N, q.spectral_frequencies(coefs), q.flatten_mlp_params(Ws, bs))
+    pos_np = W.make_positions(5)
+    pos = torch.from_numpy(pos_np).cuda()
+    net.init_output(spl.eval_vgl(pos[:4096]))
+    _say("case mlp forward, full batch B=%d" % pos_np.shape[0])
+    got = [t.cpu().numpy() for t in net.forward(pos)]
+    idx = np.sort(np.random.default_rng(3).choice(pos_np.shape[0], 512, replace=False))
+    emu = M.forward(net.params_numpy(), pos_np[idx], bf16=True)
+    e = [oracle.rel_err(g[idx], r) for g, r in zip(got, emu)]
+    _say("eps V/G/L on 512 sampled rows = %.2e %.2e %.2e" % tuple(e))
+    assert all(np.isfinite(g).all() for g in got)
+    assert max(e) <= 2.0 ** -7
+
+
 def _set_loss_weights(torch, net, w):
     lay = net.layout
     net.buf[lay.loss_w:lay.loss_w + 12] = torch.tensor(w, dtype=torch.float32).view(torch.uint8).to(net.buf.device)
