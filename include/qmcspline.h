@@ -568,7 +568,8 @@ int spline_mlp_train_step(spline_mlp_t* mlp, const double* pos, const float* tV,
                           int64_t B, float lr, void* ws, size_t ws_bytes, float* loss_out, void* stream);
 
 /* Network-only VGL (no fallback) at pos [B][3]: V [B][N], G [B][3][N],
- * L [B][N], FP32, device.  Asynchronous. */
+ * L [B][N], FP32, device, each 16-byte aligned (SPL_EINVAL otherwise).
+ * Asynchronous. */
 int spline_mlp_forward(const spline_mlp_t* mlp, const double* pos, int64_t B, float* V, float* G, float* L,
                        void* stream);
 
