@@ -595,7 +595,9 @@ int spline_mlp_build_error_map(spline_mlp_t* mlp, const spline_t* table, const d
  * rows equal spline_eval_vgl's bit for bit, the others
  * spline_mlp_forward's.  n_fallback (device int32, may be NULL) receives the
  * number routed.  ws: device workspace of spline_mlp_eval_workspace_bytes(B)
- * bytes. */
+ * bytes.  V, G, L as for spline_mlp_forward.  The fallback must have the
+ * network's N orbitals, a non-FP64 storage type (FP32 outputs) and the
+ * network's orthorhombic cell (SPL_EINVAL / SPL_EUNSUPPORTED otherwise). */
 size_t spline_mlp_eval_workspace_bytes(int64_t B);
 int spline_mlp_eval_vgl(const spline_mlp_t* mlp, const spline_t* fallback, float tol, const double* pos, int64_t B,
                         float* V, float* G, float* L, void* ws, size_t ws_bytes, int32_t* n_fallback, void* stream);
